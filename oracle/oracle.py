@@ -1,0 +1,239 @@
+"""ctypes binding of the plain C oracle (``lbm_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, the smoke check and the
+benchmark's CPU-baseline leg, never by the GPU library.
+
+Layout of every field: ``float64[19, ny, nx]`` (x fastest); scalar planes are
+``float64[ny, nx]``. Boundary codes: 0 periodic, 1 fixed equilibrium
+(Sec. III.B, Eq. (57)), 2 reflecting wall, 3 outflow (Sec. IV.A,
+Eqs. (63)-(64)). Sides are ordered x-lo, x-hi, y-lo, y-hi.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import sysconfig
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "lbm_oracle.c")
+LIB = os.path.join(HERE, "liblbm_oracle.so")
+
+PERIODIC, FIXED_EQ, REFLECT, OUTFLOW = 0, 1, 2, 3
+NV = 19
+
+__all__ = [
+    "OracleParams", "build_oracle", "lib", "velocity_table", "weights", "feq_cell",
+    "moments_cell", "weno5", "weno5_grad", "weno_periodic_line", "init", "moments",
+    "step", "kinetic_y", "kinetic_y_grad", "adjoint_step", "init_vjp", "feq_partials",
+    "PERIODIC", "FIXED_EQ", "REFLECT", "OUTFLOW", "NV",
+]
+
+
+def build_oracle(force: bool = False) -> str:
+    """Compile the oracle with gcc: -O2, no FMA contraction, no fast-math."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+           "-shared", "-std=c11", "-Wall", "-Wno-unused-function", SRC, "-o", tmp, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+class OracleParams(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("bc", C.c_int32 * 4),
+        ("dx", C.c_double), ("dy", C.c_double), ("dt", C.c_double), ("tau", C.c_double),
+        ("vk", C.c_double * 3), ("eps", C.c_double),
+        ("side_state", (C.c_double * 4) * 4),
+    ]
+
+    @classmethod
+    def make(cls, nx, ny, dx, dy, dt, tau, bc=(PERIODIC,) * 4, vk=(1.0, 2.0, 3.0),
+             eps=1e-6, side_state=None):
+        p = cls()
+        p.nx, p.ny = int(nx), int(ny)
+        for s in range(4):
+            p.bc[s] = int(bc[s])
+        p.dx, p.dy, p.dt, p.tau = float(dx), float(dy), float(dt), float(tau)
+        for k in range(3):
+            p.vk[k] = float(vk[k])
+        p.eps = float(eps)
+        if side_state is not None:
+            for s in range(4):
+                if side_state[s] is not None:
+                    for q in range(4):
+                        p.side_state[s][q] = float(side_state[s][q])
+        return p
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build_oracle())
+        d = C.c_double
+        pd = C.POINTER(C.c_double)
+        pi = C.POINTER(C.c_int32)
+        pp = C.POINTER(OracleParams)
+        _lib.orc_velocity_table.argtypes = [pd, pd, pd, pd, pi, pi, pi]
+        _lib.orc_weights.argtypes = [d, pd, pd]
+        _lib.orc_weights.restype = None
+        _lib.orc_feq_cell.argtypes = [d, d, d, d, pd, pd]
+        _lib.orc_feq_cell.restype = None
+        _lib.orc_moments_cell.argtypes = [pd, pd, pd]
+        _lib.orc_moments_cell.restype = None
+        _lib.orc_weno5.argtypes = [d, d, d, d, d, d]
+        _lib.orc_weno5.restype = d
+        _lib.orc_weno5_grad.argtypes = [d, d, d, d, d, d, pd]
+        _lib.orc_weno5_grad.restype = None
+        _lib.orc_weno_periodic_line.argtypes = [pd, C.c_int, C.c_int, d, pd]
+        _lib.orc_weno_periodic_line.restype = None
+        _lib.orc_init.argtypes = [pp, pd, pd, pd, pd, pd]
+        _lib.orc_moments.argtypes = [pp, pd, pd, pd, pd, pd]
+        _lib.orc_step.argtypes = [pp, pd, pd, C.c_int, C.c_int]
+        _lib.orc_kinetic_y.argtypes = [pp, pd, pd]
+        _lib.orc_kinetic_y_grad.argtypes = [pp, pd, pd]
+        _lib.orc_adjoint_step.argtypes = [pp, pd, pd, d, pd]
+        _lib.orc_init_vjp.argtypes = [pp, pd, pd, pd, pd, pd, pd, pd, pd, pd]
+        _lib.orc_feq_partials.argtypes = [d, d, d, d, pd, C.c_int, pd]
+        _lib.orc_feq_partials.restype = None
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _vk(vk):
+    return np.ascontiguousarray(vk, dtype=np.float64)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with code {rc}")
+
+
+def velocity_table(vk=(1.0, 2.0, 3.0)):
+    """(vx, vy, |v|^2, shell, x-mirror, y-mirror) for the 19 velocities."""
+    L = lib()
+    vx, vy, vsq = np.zeros(NV), np.zeros(NV), np.zeros(NV)
+    shell, mx, my = (np.zeros(NV, np.int32) for _ in range(3))
+    pi = C.POINTER(C.c_int32)
+    L.orc_velocity_table(_p(_vk(vk)), _p(vx), _p(vy), _p(vsq), shell.ctypes.data_as(pi),
+                         mx.ctypes.data_as(pi), my.ctypes.data_as(pi))
+    return vx, vy, vsq, shell, mx, my
+
+
+def weights(T, vk=(1.0, 2.0, 3.0)):
+    """(F_0, F_1, F_2, F_3) at temperature T."""
+    F = np.zeros(4)
+    lib().orc_weights(float(T), _p(_vk(vk)), _p(F))
+    return F
+
+
+def feq_cell(rho, ux, uy, T, vk=(1.0, 2.0, 3.0)):
+    out = np.zeros(NV)
+    lib().orc_feq_cell(float(rho), float(ux), float(uy), float(T), _p(_vk(vk)), _p(out))
+    return out
+
+
+def feq_partials(rho, ux, uy, T, i, vk=(1.0, 2.0, 3.0)):
+    out = np.zeros(4)
+    lib().orc_feq_partials(float(rho), float(ux), float(uy), float(T), _p(_vk(vk)), int(i),
+                           _p(out))
+    return out
+
+
+def moments_cell(f, vk=(1.0, 2.0, 3.0)):
+    """(rho, ux, uy, T) of one cell's 19 values."""
+    f = _f64(f)
+    out = np.zeros(4)
+    lib().orc_moments_cell(_p(f), _p(_vk(vk)), _p(out))
+    return out
+
+
+def weno5(a, b, c, d, e, eps=1e-6):
+    return lib().orc_weno5(float(a), float(b), float(c), float(d), float(e), float(eps))
+
+
+def weno5_grad(a, b, c, d, e, eps=1e-6):
+    g = np.zeros(5)
+    lib().orc_weno5_grad(float(a), float(b), float(c), float(d), float(e), float(eps), _p(g))
+    return g
+
+
+def weno_periodic_line(F, sign=1, eps=1e-6):
+    """Face fluxes h[I] at I+1/2 of a periodic line."""
+    F = _f64(F)
+    h = np.zeros_like(F)
+    lib().orc_weno_periodic_line(_p(F), F.size, int(sign), float(eps), _p(h))
+    return h
+
+
+def init(params, rho, ux, uy, T):
+    ny, nx = params.ny, params.nx
+    f = np.zeros((NV, ny, nx))
+    a = [_f64(x).reshape(ny, nx) for x in (rho, ux, uy, T)]
+    _check(lib().orc_init(C.byref(params), *[_p(x) for x in a], _p(f)), "init")
+    return f
+
+
+def moments(params, f):
+    ny, nx = params.ny, params.nx
+    f = _f64(f)
+    out = [np.zeros((ny, nx)) for _ in range(4)]
+    _check(lib().orc_moments(C.byref(params), _p(f), *[_p(x) for x in out]), "moments")
+    return tuple(out)
+
+
+def step(params, f, nsteps=1, nthreads=1):
+    f = _f64(f)
+    out = np.zeros_like(f)
+    _check(lib().orc_step(C.byref(params), _p(f), _p(out), int(nsteps), int(nthreads)),
+           "step")
+    return out
+
+
+def kinetic_y(params, f):
+    """(sum of rho uy^2/2 dx dy, max of rho uy^2/2)."""
+    f = _f64(f)
+    out = np.zeros(2)
+    _check(lib().orc_kinetic_y(C.byref(params), _p(f), _p(out)), "kinetic_y")
+    return out
+
+
+def kinetic_y_grad(params, f):
+    f = _f64(f)
+    out = np.zeros_like(f)
+    _check(lib().orc_kinetic_y_grad(C.byref(params), _p(f), _p(out)), "kinetic_y_grad")
+    return out
+
+
+def adjoint_step(params, f_n, lam_np1, w=0.0):
+    f_n = _f64(f_n)
+    lam_np1 = _f64(lam_np1)
+    out = np.zeros_like(f_n)
+    _check(lib().orc_adjoint_step(C.byref(params), _p(f_n), _p(lam_np1), float(w), _p(out)),
+           "adjoint_step")
+    return out
+
+
+def init_vjp(params, rho, ux, uy, T, lam0):
+    ny, nx = params.ny, params.nx
+    a = [_f64(x).reshape(ny, nx) for x in (rho, ux, uy, T)]
+    lam0 = _f64(lam0)
+    out = [np.zeros((ny, nx)) for _ in range(4)]
+    _check(lib().orc_init_vjp(C.byref(params), *[_p(x) for x in a], _p(lam0),
+                              *[_p(x) for x in out]), "init_vjp")
+    return tuple(out)
