@@ -1,0 +1,131 @@
+/*
+ * lbm.h -- C-ABI of the MI355X (gfx950) D2V19 + WENO5 finite-difference
+ * lattice-Boltzmann library (liblbm_hip.so).
+ *
+ * The method is the FDLB model of Gan, Xu, Zhang and Li (arXiv:1010.4124):
+ * 19 discrete velocities (Sec. II.A, Eq. (5)), closed-form weights F_k(T)
+ * (Sec. II.C, Eqs. (44)-(46)), third-order equilibrium (Eq. (28)), BGK
+ * collision (Eq. (4)), fifth-order WENO fluxes upwinded by the sign of each
+ * velocity component (Sec. III.A, Eqs. (48)-(55)) and forward-Euler time
+ * stepping (Eq. (47)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All field pointers are DEVICE pointers to float64 memory owned by the
+ *    caller. The library never frees or reallocates them.
+ *  - A distribution field is 19 planes: element (i, y, x) sits at
+ *    f[i*ny*nx + y*nx + x] (structure of arrays, x fastest). A scalar field
+ *    is one plane, element (y, x) at p[y*nx + x].
+ *  - Velocity i = 0 is the rest particle; i = 1 + 6(k-1) + (j-1) is speed
+ *    v_k (k = 1..3) in direction j (angle j*pi/3, j = 1..6).
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL is the
+ *    default stream). Device faults surface at the caller's next
+ *    synchronisation.
+ *  - Return value: LBM_OK (0) or a negative LBM_E* code; the message of the
+ *    last failure on the calling thread is returned by lbm_last_error().
+ *    No C++ exception crosses this interface.
+ *  - Input and output buffers of one call must not overlap (LBM_EINVAL where
+ *    the base pointers coincide).
+ *  - Calls on one context must not run concurrently on different streams:
+ *    a context's scratch buffers are shared by its calls.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* lbm_stream; /* hipStream_t */
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,       /* bad argument: null pointer, sizes, aliasing, parameters */
+    LBM_EUNSUPPORTED = -2, /* valid request the library does not implement */
+    LBM_EHIP = -3,         /* HIP runtime error (message in lbm_last_error) */
+    LBM_ENOMEM = -4        /* device allocation failed */
+};
+
+/* Boundary treatment of one side. */
+enum {
+    LBM_BC_PERIODIC = 0, /* wrap; both sides of an axis must be periodic */
+    LBM_BC_FIXED_EQ = 1, /* ghosts hold f^eq of side_state: Sec. III.B, Eqs. (57)-(58) */
+    LBM_BC_REFLECT = 2,  /* specular wall on the cell face: ghost -1-m holds
+                            interior cell m of the mirrored velocity (the
+                            paper has no walls; this is the shear-layer setup) */
+    LBM_BC_OUTFLOW = 3   /* zeroth-order extrapolation, Sec. IV.A, Eqs. (63)-(64):
+                            not implemented on the GPU (LBM_EUNSUPPORTED) */
+};
+
+enum { LBM_XLO = 0, LBM_XHI = 1, LBM_YLO = 2, LBM_YHI = 3 };
+
+typedef struct {
+    int32_t nx, ny;            /* cells; each >= 1, >= 3 on an axis with a non-periodic side */
+    int32_t bc[4];             /* LBM_BC_* of x-lo, x-hi, y-lo, y-hi */
+    double dx, dy, dt, tau;    /* > 0 */
+    double vk[3];              /* particle speeds, distinct and > 0; the paper uses 1, 2, 3 */
+    double weno_eps;           /* WENO regulariser, 1e-6 in Eq. (52); > 0 */
+    double side_state[4][4];   /* (rho, ux, uy, T) of each LBM_BC_FIXED_EQ side */
+} lbm_params;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Validate `p` and create a context. Allocates on the current device: one
+ * 19-plane ping-pong state (used by lbm_step when nsteps > 1), per-tile
+ * diagnostic partials and the fixed-side equilibria. Synchronous.
+ * Errors: LBM_EINVAL (null or invalid parameters), LBM_EUNSUPPORTED
+ * (an outflow side), LBM_ENOMEM, LBM_EHIP. */
+int lbm_create(const lbm_params* p, lbm_ctx** out);
+
+/* Free a context and its device buffers (synchronises the device). NULL is
+ * a no-op. */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* f = f^eq(rho, ux, uy, T) on every cell: Eq. (28) with the weights of
+ * Eqs. (44)-(46). Inputs: four scalar fields; output: one 19-plane field. */
+int lbm_init(lbm_ctx* ctx, const double* rho, const double* ux, const double* uy,
+             const double* T, double* f_out, lbm_stream stream);
+
+/* Advance nsteps >= 1 forward-Euler steps (Eq. (47)) from f_in; the result
+ * lands in f_out and f_in is left unchanged. Each step computes, per cell,
+ * the moments of Eq. (10) from f, f^eq, the WENO5 flux differences of every
+ * velocity along x and y and the BGK relaxation.
+ * ke_log: NULL, or device double[2*nsteps] receiving for each step n the
+ * transverse kinetic energy of the state the step starts from,
+ * ke_log[2n] = sum_cells rho u_y^2 / 2 * dx * dy and ke_log[2n+1] =
+ * max_cells rho u_y^2 / 2 (the Sec. IV growth diagnostic with the interface
+ * normal along y). */
+int lbm_step(lbm_ctx* ctx, const double* f_in, double* f_out, int32_t nsteps,
+             double* ke_log, lbm_stream stream);
+
+/* (rho, ux, uy, T) of f per cell, Eq. (10): rho = sum f, rho u = sum f v,
+ * rho T = sum f |v - u|^2 / 2. */
+int lbm_moments(lbm_ctx* ctx, const double* f, double* rho, double* ux, double* uy,
+                double* T, lbm_stream stream);
+
+/* out2[0] = sum_cells rho u_y^2 / 2 * dx * dy, out2[1] = max_cells
+ * rho u_y^2 / 2 of f (device double[2]). */
+int lbm_kinetic_y(lbm_ctx* ctx, const double* f, double* out2, lbm_stream stream);
+
+/* Step-kernel variants (tile shapes) for the autotuner. A variant is a pair
+ * (rows per lane R, wavefronts per workgroup NW): tiles are 64 x (R*NW)
+ * cells. Every variant computes the same result; they differ in speed only.
+ * lbm_set_step_variant selects the variant later lbm_step calls launch. */
+int lbm_step_variant_count(void);
+int lbm_step_variant_info(int32_t variant, int32_t* rows_per_lane, int32_t* waves);
+int lbm_set_step_variant(lbm_ctx* ctx, int32_t variant);
+int lbm_get_step_variant(lbm_ctx* ctx, int32_t* variant);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* lbm_last_error(void);
+
+/* Library version string. */
+const char* lbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,267 @@
+// lbm_api.hip -- host side of the C-ABI declared in include/lbm.h:
+// parameter validation, context ownership, launch sequencing and errors.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "lbm.h"
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+using namespace lbmd;
+
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, const char* a = "", long long b = 0)
+{
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), fmt, a, b);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where)
+{
+    g_err = std::string(where) + ": " + hipGetErrorString(e);
+    return LBM_EHIP;
+}
+}  // namespace
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+const char* lbm_version(void) { return "lbm_hip 0.1 gfx950 d2v19-weno5"; }
+
+int lbmi_validate(const lbm_params* p)
+{
+    if (!p) return fail(LBM_EINVAL, "params is null%s%lld");
+    if (p->nx < 1 || p->ny < 1) return fail(LBM_EINVAL, "nx, ny must be >= 1%s%lld");
+    if ((long long)p->nx * p->ny * NV >= (1ll << 31) * 8ll)
+        return fail(LBM_EINVAL, "grid too large%s%lld");
+    if (!(p->dx > 0) || !(p->dy > 0) || !(p->dt > 0) || !(p->tau > 0))
+        return fail(LBM_EINVAL, "dx, dy, dt, tau must be > 0%s%lld");
+    if (!(p->weno_eps > 0)) return fail(LBM_EINVAL, "weno_eps must be > 0%s%lld");
+    for (int k = 0; k < 3; ++k)
+        if (!(p->vk[k] > 0)) return fail(LBM_EINVAL, "vk must be > 0%s%lld");
+    if (p->vk[0] == p->vk[1] || p->vk[1] == p->vk[2] || p->vk[0] == p->vk[2])
+        return fail(LBM_EINVAL, "vk must be distinct%s%lld");
+    for (int s = 0; s < 4; ++s) {
+        if (p->bc[s] < 0 || p->bc[s] > 3) return fail(LBM_EINVAL, "unknown boundary code%s%lld");
+        if (p->bc[s] == LBM_BC_OUTFLOW)
+            return fail(LBM_EUNSUPPORTED, "outflow boundaries are not implemented%s%lld");
+        const int n = s < 2 ? p->nx : p->ny;
+        if (p->bc[s] != LBM_BC_PERIODIC && n < HALO)
+            return fail(LBM_EINVAL, "a non-periodic axis needs at least 3 cells%s%lld");
+        if (p->bc[s] == LBM_BC_FIXED_EQ && (!(p->side_state[s][0] > 0) || !(p->side_state[s][3] > 0)))
+            return fail(LBM_EINVAL, "fixed-equilibrium side needs rho > 0 and T > 0%s%lld");
+    }
+    if ((p->bc[0] == LBM_BC_PERIODIC) != (p->bc[1] == LBM_BC_PERIODIC) ||
+        (p->bc[2] == LBM_BC_PERIODIC) != (p->bc[3] == LBM_BC_PERIODIC))
+        return fail(LBM_EINVAL, "periodic must be set on both sides of an axis%s%lld");
+    return LBM_OK;
+}
+
+// Host image of the per-context constants: velocity components from the
+// exact direction tables, |v|^2/2, the folded weight polynomials of
+// Eqs. (44)-(46) and the mirror partners.
+void lbmi_fill_model(const lbm_params* p, Model* h)
+{
+    std::memset(h, 0, sizeof(*h));
+    h->vx[0] = h->vy[0] = h->hv2[0] = 0.0;
+    h->mirx[0] = h->miry[0] = 0;
+    for (int k = 0; k < 3; ++k)
+        for (int d = 0; d < 6; ++d) {
+            const int i = 1 + 6 * k + d;
+            h->vx[i] = p->vk[k] * dir_cos(d);
+            h->vy[i] = p->vk[k] * (dir_sin_sign(d) * SIN60);
+            h->hv2[i] = 0.5 * (p->vk[k] * p->vk[k]);
+            h->mirx[i] = 1 + 6 * k + mirror_x_dir(d);
+            h->miry[i] = 1 + 6 * k + mirror_y_dir(d);
+        }
+    for (int k = 0; k < 3; ++k) {
+        const double a = p->vk[k] * p->vk[k];
+        const double b = p->vk[(k + 1) % 3] * p->vk[(k + 1) % 3];
+        const double c = p->vk[(k + 2) % 3] * p->vk[(k + 2) % 3];
+        const double den = 3.0 * a * (a - b) * (a - c);
+        h->Fa[k] = 24.0 / den;
+        h->Fb[k] = -4.0 * (b + c) / den;
+        h->Fc[k] = b * c / den;
+    }
+    h->eps = p->weno_eps;
+}
+
+int lbm_create(const lbm_params* p, lbm_ctx** out)
+{
+    if (!out) return fail(LBM_EINVAL, "out is null%s%lld");
+    *out = nullptr;
+    int rc = lbmi_validate(p);
+    if (rc) return rc;
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(LBM_ENOMEM, "host allocation failed%s%lld");
+    c->p = *p;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipGetDevice");
+    }
+    Model hm;
+    lbmi_fill_model(p, &hm);
+    const size_t n = (size_t)p->nx * p->ny;
+    c->variant = lbmi_default_variant(p->nx, p->ny);
+    int maxtiles = 0;
+    for (int v = 0; v < step_variant_count(); ++v) {
+        const int t = step_ntiles(v, p->nx, p->ny);
+        if (t > maxtiles) maxtiles = t;
+    }
+    c->ke_cap = maxtiles > (int)((n + 255) / 256) ? maxtiles : (int)((n + 255) / 256);
+    if ((e = hipMalloc(&c->model, sizeof(Model))) != hipSuccess ||
+        (e = hipMalloc(&c->scratch, NV * n * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&c->ke_part, 2 * (size_t)c->ke_cap * sizeof(double))) != hipSuccess) {
+        lbm_destroy(c);
+        g_err = std::string("hipMalloc: ") + hipGetErrorString(e);
+        return LBM_ENOMEM;
+    }
+    if ((e = hipMemcpy(c->model, &hm, sizeof(Model), hipMemcpyHostToDevice)) != hipSuccess) {
+        lbm_destroy(c);
+        return hip_fail(e, "hipMemcpy model");
+    }
+    if ((e = launch_side_eq(c->model, p->side_state, nullptr)) != hipSuccess ||
+        (e = hipDeviceSynchronize()) != hipSuccess) {
+        lbm_destroy(c);
+        return hip_fail(e, "side equilibria");
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c)
+{
+    if (!c) return;
+    hipDeviceSynchronize();
+    if (c->model) hipFree(c->model);
+    if (c->scratch) hipFree(c->scratch);
+    if (c->ke_part) hipFree(c->ke_part);
+    delete c;
+}
+
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb)
+{
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + nb && y < x + na;
+}
+
+int lbm_init(lbm_ctx* c, const double* rho, const double* ux, const double* uy, const double* T,
+             double* f_out, lbm_stream stream)
+{
+    if (!c || !rho || !ux || !uy || !T || !f_out) return fail(LBM_EINVAL, "null argument%s%lld");
+    const int64_t n = (int64_t)c->p.nx * c->p.ny;
+    const size_t fb = NV * n * sizeof(double), sb = n * sizeof(double);
+    const double* ins[4] = {rho, ux, uy, T};
+    for (auto q : ins)
+        if (overlaps(q, sb, f_out, fb)) return fail(LBM_EINVAL, "input overlaps f_out%s%lld");
+    hipError_t e = launch_init(rho, ux, uy, T, f_out, c->model, n, (hipStream_t)stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_init");
+}
+
+int lbm_step(lbm_ctx* c, const double* f_in, double* f_out, int32_t nsteps, double* ke_log,
+             lbm_stream stream)
+{
+    if (!c || !f_in || !f_out) return fail(LBM_EINVAL, "null argument%s%lld");
+    if (nsteps < 1) return fail(LBM_EINVAL, "nsteps must be >= 1%s%lld");
+    const int64_t n = (int64_t)c->p.nx * c->p.ny;
+    const size_t fb = NV * n * sizeof(double);
+    if (overlaps(f_in, fb, f_out, fb)) return fail(LBM_EINVAL, "f_in overlaps f_out%s%lld");
+    if (ke_log && (overlaps(ke_log, 16 * (size_t)nsteps, f_out, fb) ||
+                   overlaps(ke_log, 16 * (size_t)nsteps, f_in, fb)))
+        return fail(LBM_EINVAL, "ke_log overlaps a field%s%lld");
+    hipStream_t st = (hipStream_t)stream;
+    const lbm_params& p = c->p;
+    const double cx = p.dt / p.dx, cy = p.dt / p.dy, ct = p.dt / p.tau;
+    const int ntiles = step_ntiles(c->variant, p.nx, p.ny);
+    for (int s = 0; s < nsteps; ++s) {
+        // step s writes f_out when (nsteps - 1 - s) is even, else the scratch
+        const double* src = s == 0 ? f_in : (((nsteps - s) % 2 == 0) ? f_out : c->scratch);
+        double* dst = ((nsteps - 1 - s) % 2 == 0) ? f_out : c->scratch;
+        hipError_t e = launch_step(c->variant, src, dst, c->model, ke_log ? c->ke_part : nullptr,
+                                   p.nx, p.ny, p.bc, cx, cy, ct, st);
+        if (e != hipSuccess) return hip_fail(e, "lbm_step");
+        if (ke_log) {
+            e = launch_reduce_pairs(c->ke_part, ntiles, p.dx * p.dy, ke_log + 2 * s, st);
+            if (e != hipSuccess) return hip_fail(e, "lbm_step ke");
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx* c, const double* f, double* rho, double* ux, double* uy, double* T,
+                lbm_stream stream)
+{
+    if (!c || !f || !rho || !ux || !uy || !T) return fail(LBM_EINVAL, "null argument%s%lld");
+    const int64_t n = (int64_t)c->p.nx * c->p.ny;
+    const size_t fb = NV * n * sizeof(double), sb = n * sizeof(double);
+    double* outs[4] = {rho, ux, uy, T};
+    for (auto q : outs)
+        if (overlaps(q, sb, f, fb)) return fail(LBM_EINVAL, "output overlaps f%s%lld");
+    hipError_t e = launch_moments(f, rho, ux, uy, T, c->model, n, (hipStream_t)stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_moments");
+}
+
+int lbm_kinetic_y(lbm_ctx* c, const double* f, double* out2, lbm_stream stream)
+{
+    if (!c || !f || !out2) return fail(LBM_EINVAL, "null argument%s%lld");
+    const int64_t n = (int64_t)c->p.nx * c->p.ny;
+    int np = 0;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = launch_kinetic_part(f, c->model, n, c->ke_part, &np, st);
+    if (e == hipSuccess) e = launch_reduce_pairs(c->ke_part, np, c->p.dx * c->p.dy, out2, st);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_kinetic_y");
+}
+
+int lbm_step_variant_count(void) { return step_variant_count(); }
+
+int lbm_step_variant_info(int32_t v, int32_t* rows_per_lane, int32_t* waves)
+{
+    int R = 0, NW = 0;
+    if (!rows_per_lane || !waves || step_variant_desc(v, &R, &NW))
+        return fail(LBM_EINVAL, "bad variant%s%lld");
+    *rows_per_lane = R;
+    *waves = NW;
+    return LBM_OK;
+}
+
+int lbm_set_step_variant(lbm_ctx* c, int32_t v)
+{
+    if (!c || v < 0 || v >= step_variant_count()) return fail(LBM_EINVAL, "bad variant%s%lld");
+    c->variant = v;
+    return LBM_OK;
+}
+
+int lbm_get_step_variant(lbm_ctx* c, int32_t* v)
+{
+    if (!c || !v) return fail(LBM_EINVAL, "null argument%s%lld");
+    *v = c->variant;
+    return LBM_OK;
+}
+
+// Default step variant: the tallest tile that does not leave most of its
+// rows empty on short grids.
+int lbmi_default_variant(int nx, int ny)
+{
+    (void)nx;
+    int best = 0, best_rows = 0;
+    for (int v = 0; v < step_variant_count(); ++v) {
+        int R = 0, NW = 0;
+        step_variant_desc(v, &R, &NW);
+        const int rows = R * NW;
+        const bool fits = rows <= ny || rows == 16;
+        if (fits && (R == 8 || best_rows == 0) && rows >= best_rows && R >= 4) {
+            best = v;
+            best_rows = rows;
+        }
+    }
+    return best;
+}

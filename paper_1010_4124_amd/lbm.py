@@ -1,0 +1,257 @@
+"""ctypes binding of liblbm_hip.so (the C-ABI of include/lbm.h).
+
+Argument marshalling only: torch tensors supply device pointers and the
+current HIP stream; every step of the computation runs in the library's HIP
+kernels. The binding refuses to run without the built library and without a
+GPU: there is no CPU fallback.
+
+Functions carry the C entry points' names (``lbm_create``, ``lbm_init``,
+``lbm_step``, ...); ``Context`` is a small owner of an ``lbm_ctx*``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm_hip.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "lbm.h")
+
+NV = 19
+PERIODIC, FIXED_EQ, REFLECT, OUTFLOW = 0, 1, 2, 3
+LBM_OK, LBM_EINVAL, LBM_EUNSUPPORTED, LBM_EHIP, LBM_ENOMEM = 0, -1, -2, -3, -4
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"liblbm_hip error {code}: {msg}")
+        self.code = code
+
+
+class LbmParams(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("bc", C.c_int32 * 4),
+        ("dx", C.c_double), ("dy", C.c_double), ("dt", C.c_double), ("tau", C.c_double),
+        ("vk", C.c_double * 3), ("weno_eps", C.c_double),
+        ("side_state", (C.c_double * 4) * 4),
+    ]
+
+    @classmethod
+    def make(cls, nx, ny, dx, dy, dt, tau, bc=(PERIODIC,) * 4, vk=(1.0, 2.0, 3.0), eps=1e-6,
+             side_state=None):
+        p = cls()
+        p.nx, p.ny = int(nx), int(ny)
+        for s in range(4):
+            p.bc[s] = int(bc[s])
+        p.dx, p.dy, p.dt, p.tau = float(dx), float(dy), float(dt), float(tau)
+        for k in range(3):
+            p.vk[k] = float(vk[k])
+        p.weno_eps = float(eps)
+        if side_state is not None:
+            for s in range(4):
+                if side_state[s] is not None:
+                    for q in range(4):
+                        p.side_state[s][q] = float(side_state[s][q])
+        return p
+
+
+_lib = None
+_P = C.c_void_p
+_I = C.c_int32
+
+
+def header_functions(path=HEADER):
+    """Names of the functions include/lbm.h declares."""
+    txt = open(path).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", txt)))
+
+
+def lib():
+    """Load liblbm_hip.so (built by paper_1010_4124_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                           "(the HIP library is the only compute path)")
+    L = C.CDLL(LIB_PATH)
+    sig = {
+        "lbm_create": (C.c_int, [C.POINTER(LbmParams), C.POINTER(C.c_void_p)]),
+        "lbm_destroy": (None, [_P]),
+        "lbm_init": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+        "lbm_step": (C.c_int, [_P, _P, _P, _I, _P, _P]),
+        "lbm_moments": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+        "lbm_kinetic_y": (C.c_int, [_P, _P, _P, _P]),
+        "lbm_step_variant_count": (C.c_int, []),
+        "lbm_step_variant_info": (C.c_int, [_I, C.POINTER(_I), C.POINTER(_I)]),
+        "lbm_set_step_variant": (C.c_int, [_P, _I]),
+        "lbm_get_step_variant": (C.c_int, [_P, C.POINTER(_I)]),
+        "lbm_last_error": (C.c_char_p, []),
+        "lbm_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name, None)
+        if fn is None:
+            continue
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != LBM_OK:
+        raise LbmError(rc, lib().lbm_last_error().decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t, shape=None, what="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{what} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("liblbm_hip needs a HIP GPU; no CPU fallback exists")
+
+
+# --- thin wrappers carrying the C names -----------------------------------
+def lbm_create(params: LbmParams):
+    _require_gpu()
+    h = C.c_void_p()
+    _check(lib().lbm_create(C.byref(params), C.byref(h)))
+    return h
+
+
+def lbm_destroy(h):
+    if h:
+        lib().lbm_destroy(h)
+
+
+def lbm_init(h, nx, ny, rho, ux, uy, T, f_out, stream=None):
+    s = (ny, nx)
+    _check(lib().lbm_init(h, _ptr(rho, s, "rho"), _ptr(ux, s, "ux"), _ptr(uy, s, "uy"),
+                          _ptr(T, s, "T"), _ptr(f_out, (NV, ny, nx), "f_out"), _stream(stream)))
+
+
+def lbm_step(h, nx, ny, f_in, f_out, nsteps=1, ke_log=None, stream=None):
+    if ke_log is not None:
+        _ptr(ke_log, (int(nsteps), 2), "ke_log")
+    _check(lib().lbm_step(h, _ptr(f_in, (NV, ny, nx), "f_in"), _ptr(f_out, (NV, ny, nx), "f_out"),
+                          int(nsteps), _ptr(ke_log), _stream(stream)))
+
+
+def lbm_moments(h, nx, ny, f, rho, ux, uy, T, stream=None):
+    s = (ny, nx)
+    _check(lib().lbm_moments(h, _ptr(f, (NV, ny, nx), "f"), _ptr(rho, s, "rho"), _ptr(ux, s, "ux"),
+                             _ptr(uy, s, "uy"), _ptr(T, s, "T"), _stream(stream)))
+
+
+def lbm_kinetic_y(h, nx, ny, f, out2, stream=None):
+    _check(lib().lbm_kinetic_y(h, _ptr(f, (NV, ny, nx), "f"), _ptr(out2, (2,), "out2"),
+                               _stream(stream)))
+
+
+def lbm_step_variant_count():
+    return int(lib().lbm_step_variant_count())
+
+
+def lbm_step_variant_info(v):
+    R, NW = _I(), _I()
+    _check(lib().lbm_step_variant_info(int(v), C.byref(R), C.byref(NW)))
+    return R.value, NW.value
+
+
+def lbm_set_step_variant(h, v):
+    _check(lib().lbm_set_step_variant(h, int(v)))
+
+
+def lbm_get_step_variant(h):
+    v = _I()
+    _check(lib().lbm_get_step_variant(h, C.byref(v)))
+    return v.value
+
+
+# --- convenience owner -------------------------------------------------------
+class Context:
+    """Owns one lbm_ctx* for a grid and its parameters."""
+
+    def __init__(self, nx, ny, dx, dy, dt, tau, bc=(PERIODIC,) * 4, vk=(1.0, 2.0, 3.0),
+                 eps=1e-6, side_state=None):
+        self.params = LbmParams.make(nx, ny, dx, dy, dt, tau, bc, vk, eps, side_state)
+        self.nx, self.ny = int(nx), int(ny)
+        self.handle = lbm_create(self.params)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    @classmethod
+    def from_setup(cls, s, **kw):
+        return cls(s.nx, s.ny, s.dx, s.dy, s.dt, s.tau, s.bc, side_state=s.side_state, **kw)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lbm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # allocation helpers (device memory comes from torch)
+    def empty_f(self):
+        return torch.empty((NV, self.ny, self.nx), dtype=torch.float64, device=self.device)
+
+    def empty_plane(self):
+        return torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+
+    def _dev(self, a):
+        if isinstance(a, torch.Tensor):
+            return a.to(device=self.device, dtype=torch.float64).contiguous()
+        return torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous()
+
+    def init(self, rho, ux, uy, T, out=None):
+        out = self.empty_f() if out is None else out
+        lbm_init(self.handle, self.nx, self.ny, *(self._dev(x) for x in (rho, ux, uy, T)), out)
+        return out
+
+    def step(self, f, nsteps=1, out=None, ke_log=False):
+        out = self.empty_f() if out is None else out
+        ke = torch.empty((int(nsteps), 2), dtype=torch.float64, device=self.device) if ke_log else None
+        lbm_step(self.handle, self.nx, self.ny, f, out, nsteps, ke)
+        return (out, ke) if ke_log else out
+
+    def moments(self, f):
+        outs = [self.empty_plane() for _ in range(4)]
+        lbm_moments(self.handle, self.nx, self.ny, f, *outs)
+        return tuple(outs)
+
+    def kinetic_y(self, f):
+        out = torch.empty(2, dtype=torch.float64, device=self.device)
+        lbm_kinetic_y(self.handle, self.nx, self.ny, f, out)
+        return out
+
+    @property
+    def variant(self):
+        return lbm_get_step_variant(self.handle)
+
+    @variant.setter
+    def variant(self, v):
+        lbm_set_step_variant(self.handle, v)

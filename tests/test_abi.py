@@ -1,0 +1,53 @@
+"""The C-ABI library loads and exports every function include/lbm.h declares
+(no compute call: these run without a GPU)."""
+import os
+
+import pytest
+
+from paper_1010_4124_amd import lbm
+
+
+def test_library_built():
+    assert os.path.exists(lbm.LIB_PATH), "run __graft_entry__.build() first"
+
+
+def test_exports_every_declared_symbol():
+    names = lbm.header_functions()
+    assert "lbm_step" in names and "lbm_init" in names and "lbm_moments" in names
+    L = lbm.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_version_and_variants_without_gpu():
+    L = lbm.lib()
+    assert b"gfx950" in L.lbm_version()
+    n = lbm.lbm_step_variant_count()
+    assert n >= 2
+    for v in range(n):
+        R, NW = lbm.lbm_step_variant_info(v)
+        assert R >= 1 and NW >= 1
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_step_variant_info(n)
+
+
+def test_create_rejects_bad_params_without_gpu():
+    """Parameter validation happens before any device work."""
+    import ctypes as C
+    L = lbm.lib()
+    bad = [
+        lbm.LbmParams.make(0, 4, 1e-3, 1e-3, 1e-5, 1e-5),
+        lbm.LbmParams.make(8, 8, 1e-3, 1e-3, -1e-5, 1e-5),
+        lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 0.0),
+        lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5, vk=(1, 1, 3)),
+        lbm.LbmParams.make(2, 8, 1e-3, 1e-3, 1e-5, 1e-5, bc=(2, 2, 0, 0)),
+        lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5, bc=(0, 2, 0, 0)),
+        lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5, bc=(1, 1, 0, 0)),  # side rho = 0
+    ]
+    for p in bad:
+        h = C.c_void_p()
+        assert L.lbm_create(C.byref(p), C.byref(h)) == lbm.LBM_EINVAL
+        assert L.lbm_last_error()
+    p = lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5, bc=(3, 3, 0, 0))
+    h = C.c_void_p()
+    assert L.lbm_create(C.byref(p), C.byref(h)) == lbm.LBM_EUNSUPPORTED
