@@ -67,7 +67,7 @@ int lbmi_validate(const lbm_params* p)
 // Host image of the per-context constants: velocity components from the
 // exact direction tables, |v|^2/2, the folded weight polynomials of
 // Eqs. (44)-(46) and the mirror partners.
-void lbmi_fill_model(const lbm_params* p, Model* h)
+void lbmi_fill_consts(const lbm_params* p, Consts* h)
 {
     std::memset(h, 0, sizeof(*h));
     h->vx[0] = h->vy[0] = h->hv2[0] = 0.0;
@@ -107,8 +107,7 @@ int lbm_create(const lbm_params* p, lbm_ctx** out)
         delete c;
         return hip_fail(e, "hipGetDevice");
     }
-    Model hm;
-    lbmi_fill_model(p, &hm);
+    lbmi_fill_consts(p, &c->k);
     const size_t n = (size_t)p->nx * p->ny;
     c->variant = lbmi_default_variant(p->nx, p->ny);
     int maxtiles = 0;
@@ -117,19 +116,20 @@ int lbm_create(const lbm_params* p, lbm_ctx** out)
         if (t > maxtiles) maxtiles = t;
     }
     c->ke_cap = maxtiles > (int)((n + 255) / 256) ? maxtiles : (int)((n + 255) / 256);
-    if ((e = hipMalloc(&c->model, sizeof(Model))) != hipSuccess ||
-        (e = hipMalloc(&c->scratch, NV * n * sizeof(double))) != hipSuccess ||
+    // the same buffer first receives the 4 x 19 fixed-side equilibria
+    if (2 * c->ke_cap < 4 * NV) c->ke_cap = 2 * NV;
+    if ((e = hipMalloc(&c->scratch, NV * n * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&c->ke_part, 2 * (size_t)c->ke_cap * sizeof(double))) != hipSuccess) {
         lbm_destroy(c);
         g_err = std::string("hipMalloc: ") + hipGetErrorString(e);
         return LBM_ENOMEM;
     }
-    if ((e = hipMemcpy(c->model, &hm, sizeof(Model), hipMemcpyHostToDevice)) != hipSuccess) {
-        lbm_destroy(c);
-        return hip_fail(e, "hipMemcpy model");
-    }
-    if ((e = launch_side_eq(c->model, p->side_state, nullptr)) != hipSuccess ||
-        (e = hipDeviceSynchronize()) != hipSuccess) {
+    // f^eq of the fixed sides, evaluated on the device by the same
+    // equilibrium code as every other cell, then kept in the constants
+    if ((e = launch_side_eq(c->ke_part, p->side_state, c->k, nullptr)) != hipSuccess ||
+        (e = hipDeviceSynchronize()) != hipSuccess ||
+        (e = hipMemcpy(&c->k.side_eq[0][0], c->ke_part, sizeof(c->k.side_eq),
+                       hipMemcpyDeviceToHost)) != hipSuccess) {
         lbm_destroy(c);
         return hip_fail(e, "side equilibria");
     }
@@ -141,7 +141,6 @@ void lbm_destroy(lbm_ctx* c)
 {
     if (!c) return;
     hipDeviceSynchronize();
-    if (c->model) hipFree(c->model);
     if (c->scratch) hipFree(c->scratch);
     if (c->ke_part) hipFree(c->ke_part);
     delete c;
@@ -163,7 +162,7 @@ int lbm_init(lbm_ctx* c, const double* rho, const double* ux, const double* uy, 
     const double* ins[4] = {rho, ux, uy, T};
     for (auto q : ins)
         if (overlaps(q, sb, f_out, fb)) return fail(LBM_EINVAL, "input overlaps f_out%s%lld");
-    hipError_t e = launch_init(rho, ux, uy, T, f_out, c->model, n, (hipStream_t)stream);
+    hipError_t e = launch_init(rho, ux, uy, T, f_out, c->k, n, (hipStream_t)stream);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_init");
 }
 
@@ -186,7 +185,7 @@ int lbm_step(lbm_ctx* c, const double* f_in, double* f_out, int32_t nsteps, doub
         // step s writes f_out when (nsteps - 1 - s) is even, else the scratch
         const double* src = s == 0 ? f_in : (((nsteps - s) % 2 == 0) ? f_out : c->scratch);
         double* dst = ((nsteps - 1 - s) % 2 == 0) ? f_out : c->scratch;
-        hipError_t e = launch_step(c->variant, src, dst, c->model, ke_log ? c->ke_part : nullptr,
+        hipError_t e = launch_step(c->variant, src, dst, c->k, ke_log ? c->ke_part : nullptr,
                                    p.nx, p.ny, p.bc, cx, cy, ct, st);
         if (e != hipSuccess) return hip_fail(e, "lbm_step");
         if (ke_log) {
@@ -206,7 +205,7 @@ int lbm_moments(lbm_ctx* c, const double* f, double* rho, double* ux, double* uy
     double* outs[4] = {rho, ux, uy, T};
     for (auto q : outs)
         if (overlaps(q, sb, f, fb)) return fail(LBM_EINVAL, "output overlaps f%s%lld");
-    hipError_t e = launch_moments(f, rho, ux, uy, T, c->model, n, (hipStream_t)stream);
+    hipError_t e = launch_moments(f, rho, ux, uy, T, c->k, n, (hipStream_t)stream);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_moments");
 }
 
@@ -216,20 +215,22 @@ int lbm_kinetic_y(lbm_ctx* c, const double* f, double* out2, lbm_stream stream)
     const int64_t n = (int64_t)c->p.nx * c->p.ny;
     int np = 0;
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = launch_kinetic_part(f, c->model, n, c->ke_part, &np, st);
+    hipError_t e = launch_kinetic_part(f, c->k, n, c->ke_part, &np, st);
     if (e == hipSuccess) e = launch_reduce_pairs(c->ke_part, np, c->p.dx * c->p.dy, out2, st);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_kinetic_y");
 }
 
 int lbm_step_variant_count(void) { return step_variant_count(); }
 
-int lbm_step_variant_info(int32_t v, int32_t* rows_per_lane, int32_t* waves)
+int lbm_step_variant_info(int32_t v, int32_t* rows_per_lane, int32_t* groups,
+                          int32_t* waves_per_simd)
 {
-    int R = 0, NW = 0;
-    if (!rows_per_lane || !waves || step_variant_desc(v, &R, &NW))
+    int R = 0, G = 0, W = 0;
+    if (!rows_per_lane || !groups || !waves_per_simd || step_variant_desc(v, &R, &G, &W))
         return fail(LBM_EINVAL, "bad variant%s%lld");
     *rows_per_lane = R;
-    *waves = NW;
+    *groups = G;
+    *waves_per_simd = W;
     return LBM_OK;
 }
 
@@ -247,21 +248,18 @@ int lbm_get_step_variant(lbm_ctx* c, int32_t* v)
     return LBM_OK;
 }
 
-// Default step variant: the tallest tile that does not leave most of its
-// rows empty on short grids.
+// Default step variant: enough workgroups to cover the 256 CUs several times
+// over, with the longest strips (fewest redundant faces) that allows.
 int lbmi_default_variant(int nx, int ny)
 {
-    (void)nx;
-    int best = 0, best_rows = 0;
+    const long long cells = (long long)nx * ny;
+    int want_R = cells >= (1ll << 21) ? 8 : 4;
+    int want_G = cells >= (1ll << 21) ? 1 : 3;
+    if (ny < 8) want_R = 2;
     for (int v = 0; v < step_variant_count(); ++v) {
-        int R = 0, NW = 0;
-        step_variant_desc(v, &R, &NW);
-        const int rows = R * NW;
-        const bool fits = rows <= ny || rows == 16;
-        if (fits && (R == 8 || best_rows == 0) && rows >= best_rows && R >= 4) {
-            best = v;
-            best_rows = rows;
-        }
+        int R = 0, G = 0, W = 0;
+        step_variant_desc(v, &R, &G, &W);
+        if (R == want_R && G == want_G) return v;
     }
-    return best;
+    return 0;
 }

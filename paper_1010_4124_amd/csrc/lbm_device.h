@@ -30,9 +30,9 @@ constexpr double SIN60 = 0.86602540378443864676;  // sqrt(3)/2
 __host__ __device__ constexpr int mirror_y_dir(int d) { return d <= 4 ? 4 - d : 5; }
 __host__ __device__ constexpr int mirror_x_dir(int d) { return (7 - d) % 6; }
 
-// Per-context constants, resident in device memory and read with scalar
-// loads (every index into them is wavefront-uniform).
-struct Model {
+// Per-context constants. They travel by value in kernel arguments, so every
+// (wavefront-uniform) index into them becomes a scalar load.
+struct Consts {
     double vx[NV], vy[NV];  // v_i components
     double hv2[NV];         // |v_i|^2 / 2
     // F_k(T) = T (Fc + T (Fb + T Fa)) for k = 1..3: the closed form of
@@ -40,12 +40,13 @@ struct Model {
     double Fa[3], Fb[3], Fc[3];
     double eps;             // WENO regulariser of Eq. (52)
     double side_eq[4][NV];  // f^eq of each fixed-equilibrium side
-    int mirx[NV], miry[NV];
+    int mirx[NV], miry[NV]; // indices of (-vx, vy) and (vx, -vy)
 };
 
-__device__ __forceinline__ double weight_k(const Model* M, int k, double T)
+// F_k(T) of speed shell s = k-1 (Eqs. (44)-(46)).
+__device__ __forceinline__ double weight_c(const Consts& k, int s, double T)
 {
-    return T * __builtin_fma(T, __builtin_fma(T, M->Fa[k], M->Fb[k]), M->Fc[k]);
+    return T * __builtin_fma(T, __builtin_fma(T, k.Fa[s], k.Fb[s]), k.Fc[s]);
 }
 
 // Per-cell quantities the equilibrium needs, from the raw sums of Eq. (10):

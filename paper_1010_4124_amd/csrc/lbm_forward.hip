@@ -1,30 +1,36 @@
 // lbm_forward.hip -- forward kernels of liblbm_hip for gfx950 (MI355X).
 //
-// One launch of k_step advances every cell of the grid by one forward-Euler
-// step of the D2V19 FDLB model (Eq. (47) of arXiv:1010.4124). A workgroup of
-// NW wavefronts owns a tile of 64 x (R*NW) cells; each wavefront owns 64
-// columns x R rows and each lane a column strip of R cells.
+// One launch of k_step advances every cell by one forward-Euler step of the
+// D2V19 FDLB model (Eq. (47) of arXiv:1010.4124). Work is split into
+// one-wavefront workgroups, each owning a tile of 64 columns x R rows and one
+// of G groups of the 18 moving velocities; each lane owns a column strip of R
+// cells.
 //
-//   phase 1  every lane loads the 19 values of its R cells, forms the
-//            moments of Eq. (10) and keeps rho, T, u/T and 1-u^2/2T in
-//            registers; the rest particle is relaxed and stored at once.
-//   phase 2  for each moving velocity i = 1..18:
-//            - the tile's plane f_i plus a 3-cell cross-shaped halo (ghosts
-//              from the boundary rule) is staged in LDS; the plane after it
-//              is already in flight into registers (software pipeline);
+//   phase 1  every lane loads the 19 values of its R cells, forms the moments
+//            of Eq. (10) and keeps u/T, 1-u^2/2T and rho F_k(T) in
+//            registers. Group 0 also relaxes and stores the rest particle and
+//            reduces the tile's transverse kinetic energy.
+//   phase 2  for each velocity i of the group:
+//            - plane f_i of the tile plus a 3-cell cross-shaped halo (ghosts
+//              from the boundary rule) is staged in LDS; the next plane is
+//              already in flight into registers (software pipeline);
 //            - x pass: lanes re-map to row strips of R cells and compute the
 //              R+1 WENO faces of their strip once, sharing first and second
 //              differences between faces; flux differences go to LDS;
-//            - y pass (v_iy != 0): lanes compute the R+1 faces of their
-//              column strip in registers;
+//            - y pass (v_iy != 0): lanes compute the R+1 faces of their column
+//              strip in registers;
 //            - each lane combines convection, BGK relaxation toward f^eq and
-//              the Euler update, and stores f_i^{n+1} (coalesced along x).
+//              the Euler update and stores f_i^{n+1} (coalesced along x).
 //
-// Tiles are assigned XCD-major: consecutive workgroups are dispatched
-// round-robin over the 8 XCDs, so workgroup b takes tile
-// (b % 8) * per_xcd + b / 8 and every XCD sweeps one contiguous band of
-// tiles whose halos then meet in that XCD's L2.
+// A tile's G workgroups repeat phase 1 (the 19 centre values come from L2);
+// G > 1 multiplies the number of workgroups on small grids. Workgroups are
+// assigned XCD-major: hardware dispatches consecutive workgroups round-robin
+// over the 8 XCDs, so workgroup b takes work item (b % 8) * per_xcd + b / 8
+// and every XCD sweeps one contiguous band of tiles whose halos then meet in
+// that XCD's L2. The per-context constants travel by value in the kernel
+// arguments and are read with scalar loads.
 #include "lbm_device.h"
+#include "lbm_internal.h"
 
 namespace lbmd {
 
@@ -35,134 +41,216 @@ constexpr int XPITCH = 65;  // LDS row pitch of the x flux differences
 struct StepArgs {
     const double* __restrict__ fin;
     double* __restrict__ fout;
-    const Model* __restrict__ M;
     double* __restrict__ ke_part;  // [ntiles][2] or null
     int nx, ny;
-    int bc0, bc1, bc2, bc3;
-    int tiles_x, ntiles, per_xcd;
+    int bc[4];
+    int tiles_x, ntiles, nwork, per_xcd;
     double cx, cy, ct;  // dt/dx, dt/dy, dt/tau
+    Consts k;
 };
 
-__device__ __forceinline__ int side_bc(const StepArgs& a, int s)
-{
-    return s == 0 ? a.bc0 : s == 1 ? a.bc1 : s == 2 ? a.bc2 : a.bc3;
-}
+// ---------------------------------------------------------------------------
+// Staging of one plane of a tile into LDS.
+//
+// The staged image has R+6 rows (three halo rows above and below the tile) of
+// PITCH doubles; column lx = -3..66 sits at lx+3. Every row is one 64-lane
+// load (lane = column 0..63) from a wavefront-uniform row base; the six halo
+// columns of the R centre rows come from one more load in which lane l < 6R
+// takes row l/6 and column -3,-2,-1,64,65,66. A plane thus costs R+7 loads
+// per lane.
+//
+// Interior tiles (tile plus halo inside the domain) need nothing else. A tile
+// touching the boundary gets a per-lane column map once (source column and
+// kind of the row-load lane and of the halo lane) and resolves ghost rows with
+// uniform logic: a row outside the domain is a periodic wrap, a mirror row of
+// the y-mirrored velocity (reflecting wall), a constant (fixed equilibrium) or
+// unused. Constants and unused slots are substituted when the staged values
+// are written to LDS, so no load result is consumed before the next plane.
+enum { CK_NORM = 0, CK_MIRX = 1, CK_CXLO = 2, CK_CXHI = 3, CK_NONE = 4 };
+enum { RM_NORM = 0, RM_MIRY = 1, RM_CONST = 2, RM_NONE = 3 };
 
-// Value of plane i at (gx, gy) for a position inside the domain or in the
-// three-cell ghost layer of one side (never a corner for an active cell).
-__device__ __forceinline__ double ghost_or_value(const StepArgs& a, int i, int gx, int gy,
-                                                 int64_t plane)
-{
-    const bool inx = (unsigned)gx < (unsigned)a.nx;
-    const bool iny = (unsigned)gy < (unsigned)a.ny;
-    const Model* M = a.M;
-    if (inx && iny) return a.fin[i * plane + (int64_t)gy * a.nx + gx];
-    if (inx == iny) return 0.0;  // corner or beyond: never read by an active cell
-    if (!inx) {
-        const int side = gx < 0 ? XLO : XHI;
-        const int m = gx < 0 ? -1 - gx : gx - a.nx;
-        if (m >= HALO) return 0.0;
-        const int bc = side_bc(a, side);
-        if (bc == PERIODIC)
-            return a.fin[i * plane + (int64_t)gy * a.nx + wrap_index(gx, a.nx)];
-        if (bc == FIXED_EQ) return M->side_eq[side][i];
-        // reflect: interior cell m of the x-mirrored velocity
-        return a.fin[M->mirx[i] * plane + (int64_t)gy * a.nx + (gx < 0 ? m : a.nx - 1 - m)];
-    }
-    const int side = gy < 0 ? YLO : YHI;
-    const int m = gy < 0 ? -1 - gy : gy - a.ny;
-    if (m >= HALO) return 0.0;
-    const int bc = side_bc(a, side);
-    if (bc == PERIODIC)
-        return a.fin[i * plane + (int64_t)wrap_index(gy, a.ny) * a.nx + gx];
-    if (bc == FIXED_EQ) return M->side_eq[side][i];
-    return a.fin[M->miry[i] * plane + (int64_t)(gy < 0 ? m : a.ny - 1 - m) * a.nx + gx];
-}
-
-// Staged region of a tile: TY rows of 70 (64 + 2*3 halo columns), then six
-// halo rows of 64 (three above, three below).
-template <int TY>
+template <int R>
 struct Stage {
-    static constexpr int NEX = TY * (TX + 2 * HALO);
-    static constexpr int NE = NEX + 2 * HALO * TX;
-    __device__ static __forceinline__ void pos(int e, int& ly, int& lx)
-    {
-        if (e < NEX) {
-            ly = e / (TX + 2 * HALO);
-            lx = e - ly * (TX + 2 * HALO) - HALO;
-        } else {
-            const int e2 = e - NEX;
-            const int hr = e2 / TX;
-            lx = e2 - hr * TX;
-            ly = hr < HALO ? hr - HALO : TY + hr - HALO;
-        }
-    }
+    static constexpr int ROWS = R + 2 * HALO;
+    static constexpr int NPRE = ROWS + 1;
+    static constexpr int PAD = ROWS * PITCH;  // 64 pad slots for idle halo lanes
+    static constexpr int SLOTS = PAD + 64;
+    static_assert(6 * R <= 64, "the x-halo of the tile must fit one 64-lane load");
 };
 
-template <int TY, int NT, int NPRE>
-__device__ __forceinline__ void stage_load(const StepArgs& a, int i, int x0, int y0, bool interior,
-                                           int64_t plane, double (&pre)[NPRE])
+struct TileMap {
+    int hrow, hlx;     // halo lane: tile row and column (-3..-1, 64..66)
+    int mcol, mkind;   // row-load lane: source column and kind (boundary tiles)
+    int hcol, hkind;   // halo lane: source column and kind (boundary tiles)
+};
+
+// Source column of global column gx for a row inside the domain.
+__device__ __forceinline__ void x_source(const StepArgs& a, int gx, int& col, int& kind)
 {
-    const int tid = threadIdx.x;
+    if (gx >= 0 && gx < a.nx) {
+        col = gx;
+        kind = CK_NORM;
+        return;
+    }
+    const bool lo = gx < 0;
+    const int m = lo ? -1 - gx : gx - a.nx;
+    col = 0;
+    kind = CK_NONE;
+    if (m >= HALO) return;
+    const int bc = lo ? a.bc[XLO] : a.bc[XHI];
+    if (bc == PERIODIC) {
+        col = wrap_index(gx, a.nx);
+        kind = CK_NORM;
+    } else if (bc == REFLECT) {
+        col = lo ? m : a.nx - 1 - m;
+        kind = CK_MIRX;
+    } else {
+        kind = lo ? CK_CXLO : CK_CXHI;
+    }
+}
+
+template <int R>
+__device__ __forceinline__ TileMap tile_map(const StepArgs& a, int x0, int y0, int lane, bool bnd)
+{
+    TileMap t;
+    const bool hl = lane < 6 * R;
+    const int r = lane / 6, c = lane - 6 * (lane / 6);
+    t.hrow = hl ? r : 0;
+    t.hlx = hl ? (c < 3 ? c - 3 : c + 61) : 0;
+    t.mcol = lane;
+    t.mkind = CK_NORM;
+    t.hcol = 0;
+    t.hkind = CK_NONE;
+    if (bnd) {
+        x_source(a, x0 + lane, t.mcol, t.mkind);
+        if (hl && y0 + r < a.ny) x_source(a, x0 + t.hlx, t.hcol, t.hkind);
+    }
+    return t;
+}
+
+// Uniform description of global row gy: mode and source row.
+struct RowDesc {
+    int mode, src, side;
+};
+
+__device__ __forceinline__ RowDesc row_desc(const StepArgs& a, int gy)
+{
+    RowDesc d{RM_NORM, gy, 0};
+    if (gy >= 0 && gy < a.ny) return d;
+    const bool lo = gy < 0;
+    const int m = lo ? -1 - gy : gy - a.ny;
+    d.side = lo ? YLO : YHI;
+    d.src = 0;
+    if (m >= HALO) {
+        d.mode = RM_NONE;
+        return d;
+    }
+    const int bc = lo ? a.bc[YLO] : a.bc[YHI];
+    if (bc == PERIODIC) {
+        d.src = wrap_index(gy, a.ny);
+    } else if (bc == REFLECT) {
+        d.mode = RM_MIRY;
+        d.src = lo ? m : a.ny - 1 - m;
+    } else {
+        d.mode = RM_CONST;
+    }
+    return d;
+}
+
+template <int R, bool BND>
+__device__ __forceinline__ void stage_load(const StepArgs& a, int i, int x0, int y0, int lane,
+                                           const TileMap& t, int64_t plane,
+                                           double (&pre)[Stage<R>::NPRE])
+{
+    if (!BND) {
+        const double* base = a.fin + i * plane + (int64_t)(y0 - HALO) * a.nx + x0;
 #pragma unroll
-    for (int j = 0; j < NPRE; ++j) {
-        const int e = tid + j * NT;
-        double v = 0.0;
-        if (e < Stage<TY>::NE) {
-            int ly, lx;
-            Stage<TY>::pos(e, ly, lx);
-            const int gx = x0 + lx, gy = y0 + ly;
-            if (interior)
-                v = a.fin[i * plane + (int64_t)gy * a.nx + gx];
+        for (int r = 0; r < Stage<R>::ROWS; ++r) pre[r] = base[(int64_t)r * a.nx + lane];
+        const double* hb = a.fin + i * plane + (int64_t)y0 * a.nx + x0;
+        pre[Stage<R>::ROWS] = hb[t.hrow * a.nx + t.hlx];
+    } else {
+        const int64_t pi = i * plane, px = a.k.mirx[i] * plane, py = a.k.miry[i] * plane;
+#pragma unroll
+        for (int r = 0; r < Stage<R>::ROWS; ++r) {
+            const RowDesc d = row_desc(a, y0 - HALO + r);
+            int64_t off;
+            if (d.mode == RM_NORM)
+                off = (t.mkind == CK_MIRX ? px : pi) + (int64_t)d.src * a.nx + t.mcol;
+            else if (d.mode == RM_MIRY)
+                off = py + (int64_t)d.src * a.nx + t.mcol;
             else
-                v = ghost_or_value(a, i, gx, gy, plane);
+                off = 0;
+            pre[r] = a.fin[off];
         }
-        pre[j] = v;
+        const int64_t hoff = t.hkind == CK_NONE
+                                 ? 0
+                                 : (t.hkind == CK_MIRX ? px : pi) + (int64_t)(y0 + t.hrow) * a.nx + t.hcol;
+        pre[Stage<R>::ROWS] = a.fin[hoff];
     }
 }
 
-template <int TY, int NT, int NPRE>
-__device__ __forceinline__ void stage_store(double* s_pl, const double (&pre)[NPRE])
+template <int R, bool BND>
+__device__ __forceinline__ void stage_store(const StepArgs& a, int i, int y0, int lane,
+                                            const TileMap& t, double* s_pl,
+                                            const double (&pre)[Stage<R>::NPRE])
 {
-    const int tid = threadIdx.x;
+    if (!BND) {
 #pragma unroll
-    for (int j = 0; j < NPRE; ++j) {
-        const int e = tid + j * NT;
-        if (e < Stage<TY>::NE) {
-            int ly, lx;
-            Stage<TY>::pos(e, ly, lx);
-            s_pl[(ly + HALO) * PITCH + lx + HALO] = pre[j];
+        for (int r = 0; r < Stage<R>::ROWS; ++r) s_pl[r * PITCH + lane + HALO] = pre[r];
+    } else {
+        const double cxl = a.k.side_eq[XLO][i], cxh = a.k.side_eq[XHI][i];
+#pragma unroll
+        for (int r = 0; r < Stage<R>::ROWS; ++r) {
+            const RowDesc d = row_desc(a, y0 - HALO + r);
+            double v = pre[r];
+            if (d.mode == RM_CONST)
+                v = a.k.side_eq[d.side][i];
+            else if (d.mode == RM_NONE)
+                v = 0.0;
+            else if (d.mode == RM_NORM)
+                v = t.mkind == CK_CXLO ? cxl
+                    : t.mkind == CK_CXHI ? cxh
+                    : t.mkind == CK_NONE ? 0.0
+                                         : v;
+            s_pl[r * PITCH + lane + HALO] = v;
         }
     }
+    double h = pre[Stage<R>::ROWS];
+    if (BND)
+        h = t.hkind == CK_CXLO ? a.k.side_eq[XLO][i]
+            : t.hkind == CK_CXHI ? a.k.side_eq[XHI][i]
+            : t.hkind == CK_NONE ? 0.0
+                                 : h;
+    const int slot = lane < 6 * R ? (t.hrow + HALO) * PITCH + t.hlx + HALO : Stage<R>::PAD + lane;
+    s_pl[slot] = h;
 }
 
-// x pass: lane -> (row r = lane % R, strip s = lane / R) of this wave's R rows.
+// x pass: lane -> (row r = lane % R, strip s = lane / R).
 template <int R, bool NEG>
-__device__ __forceinline__ void x_pass(const double* s_pl, double* s_dx, int w, int lane, double v,
+__device__ __forceinline__ void x_pass(const double* s_pl, double* s_dx, int lane, double v,
                                        double eps)
 {
     const int r = lane % R, s = lane / R;
-    const int row = w * R + r;
-    const double* b = s_pl + (row + HALO) * PITCH + s * R;
+    const double* b = s_pl + (r + HALO) * PITCH + s * R;
     double P[R + 5];
 #pragma unroll
     for (int k = 0; k < R + 5; ++k) P[k] = v * (NEG ? b[R + 5 - k] : b[k]);
     double hq[R + 1];
     weno_faces<R>(P, eps, hq);
-    double* out = s_dx + row * XPITCH + s * R;
+    double* out = s_dx + r * XPITCH + s * R;
 #pragma unroll
     for (int m = 0; m < R; ++m) out[m] = NEG ? (hq[R - m - 1] - hq[R - m]) : (hq[m + 1] - hq[m]);
 }
 
-// y pass: lane = column, R rows of this wave. Also returns the centre values.
+// y pass: lane = column; also returns the centre values of the strip.
 template <int R, bool NEG>
-__device__ __forceinline__ void y_pass(const double* s_pl, int w, int lane, double v, double eps,
+__device__ __forceinline__ void y_pass(const double* s_pl, int lane, double v, double eps,
                                        double (&dhy)[R], double (&fc)[R])
 {
     const double* col = s_pl + lane + HALO;
     double fw[R + 5];
 #pragma unroll
-    for (int k = 0; k < R + 5; ++k) fw[k] = NEG ? col[(w * R + R + 5 - k) * PITCH] : col[(w * R + k) * PITCH];
+    for (int k = 0; k < R + 5; ++k) fw[k] = NEG ? col[(R + 5 - k) * PITCH] : col[k * PITCH];
 #pragma unroll
     for (int m = 0; m < R; ++m) fc[m] = NEG ? fw[R + 2 - m] : fw[m + 3];
     double P[R + 5];
@@ -187,26 +275,90 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-template <int R, int NW>
-__global__ __launch_bounds__(64 * NW) void k_step(StepArgs a)
+// Phase 2 of one tile: this group's moving velocities. Instantiated once for
+// interior tiles and once for boundary tiles, so that each loop is straight
+// line code and the compiler tracks its outstanding loads and stores exactly.
+template <int R, int G, bool BND>
+__device__ __forceinline__ void plane_loop(const StepArgs& a, int grp, int x0, int y0, int lane,
+                                           const TileMap& t, int64_t plane, double* s_pl,
+                                           double* s_dx, const double (&rho)[R],
+                                           const double (&Tm)[R], const double (&uxt)[R],
+                                           const double (&uyt)[R], const double (&t0)[R])
 {
-    constexpr int TY = R * NW;
-    constexpr int NT = 64 * NW;
-    constexpr int NPRE = (Stage<TY>::NE + NT - 1) / NT;
-    __shared__ double s_pl[(TY + 2 * HALO) * PITCH];
-    __shared__ double s_dx[TY * XPITCH];
-    __shared__ double s_red[2 * NW];
+    constexpr int NPL = 18 / G;  // moving velocities per group
+    const int gx = x0 + lane;
+    const int i0 = 1 + grp * NPL;
+    double pre[Stage<R>::NPRE];
+    stage_load<R, BND>(a, i0, x0, y0, lane, t, plane, pre);
+    stage_store<R, BND>(a, i0, y0, lane, t, s_pl, pre);
+    __syncthreads();
+    double A[R];
+    int kcur = -1;
+    // Each iteration computes the plane already in LDS. The next plane's loads
+    // are issued first (unconditionally: the last iteration re-reads its own
+    // plane) and consumed only after this plane's stores, all inside one
+    // iteration, so waiting for them never waits for the stores.
+#pragma unroll 1
+    for (int i = i0; i < i0 + NPL; ++i) {
+        const int k = (i - 1) / 6;
+        if (k != kcur) {
+            kcur = k;
+#pragma unroll
+            for (int m = 0; m < R; ++m) A[m] = rho[m] * weight_c(a.k, k, Tm[m]);
+        }
+        const int inext = i + 1 < i0 + NPL ? i + 1 : i;
+        stage_load<R, BND>(a, inext, x0, y0, lane, t, plane, pre);
+
+        const double vx = a.k.vx[i], vy = a.k.vy[i], eps = a.k.eps;
+        if (vx < 0.0)
+            x_pass<R, true>(s_pl, s_dx, lane, vx, eps);
+        else
+            x_pass<R, false>(s_pl, s_dx, lane, vx, eps);
+        double dhy[R], fc[R];
+        if (vy > 0.0) {
+            y_pass<R, false>(s_pl, lane, vy, eps, dhy, fc);
+        } else if (vy < 0.0) {
+            y_pass<R, true>(s_pl, lane, vy, eps, dhy, fc);
+        } else {
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                fc[m] = s_pl[(m + HALO) * PITCH + lane + HALO];
+                dhy[m] = 0.0;
+            }
+        }
+        __syncthreads();
+        double* dst = a.fout + i * plane + (int64_t)y0 * a.nx + gx;
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const double dhx = s_dx[m * XPITCH + lane];
+            const double eta = __builtin_fma(vx, uxt[m], vy * uyt[m]);
+            const double fe = A[m] * feq_poly(eta, t0[m]);
+            double fn = __builtin_fma(-a.cx, dhx, fc[m]);
+            fn = __builtin_fma(-a.cy, dhy[m], fn);
+            fn = __builtin_fma(-a.ct, fc[m] - fe, fn);
+            if (!BND || (gx < a.nx && y0 + m < a.ny)) dst[(int64_t)m * a.nx] = fn;
+        }
+        stage_store<R, BND>(a, inext, y0, lane, t, s_pl, pre);
+        __syncthreads();
+    }
+}
+
+template <int R, int G, int W>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_step(StepArgs a)
+{
+    __shared__ double s_pl[Stage<R>::SLOTS];
+    __shared__ double s_dx[R * XPITCH];
 
     const int b = blockIdx.x;
-    const int tile = (b & 7) * a.per_xcd + (b >> 3);
-    if (tile >= a.ntiles) return;  // uniform over the workgroup
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int work = (b & 7) * a.per_xcd + (b >> 3);
+    if (work >= a.nwork) return;
+    const int tile = work / G, grp = work - tile * G;
+    const int lane = threadIdx.x;
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
-    const int x0 = tx * TX, y0 = ty * TY;
+    const int x0 = tx * TX, y0 = ty * R;
     const int64_t plane = (int64_t)a.nx * a.ny;
-    const Model* M = a.M;
     const bool interior =
-        x0 >= HALO && x0 + TX + HALO <= a.nx && y0 >= HALO && y0 + TY + HALO <= a.ny;
+        x0 >= HALO && x0 + TX + HALO <= a.nx && y0 >= HALO && y0 + R + HALO <= a.ny;
     const int gx = x0 + lane;
 
     // ---- phase 1: moments, equilibrium data, rest particle, diagnostics ----
@@ -214,7 +366,7 @@ __global__ __launch_bounds__(64 * NW) void k_step(StepArgs a)
     double ke_s = 0.0, ke_m = 0.0;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-        const int gy = y0 + w * R + m;
+        const int gy = y0 + m;
         const bool act = gx < a.nx && gy < a.ny;
         double r = 1.0, jx = 0.0, jy = 0.0, E = 1.0, fz = 0.0;
         if (act) {
@@ -226,9 +378,9 @@ __global__ __launch_bounds__(64 * NW) void k_step(StepArgs a)
                 const double fi = p[i * plane];
                 if (i == 0) fz = fi;
                 r += fi;
-                jx = __builtin_fma(fi, M->vx[i], jx);
-                jy = __builtin_fma(fi, M->vy[i], jy);
-                E = __builtin_fma(fi, M->hv2[i], E);
+                jx = __builtin_fma(fi, a.k.vx[i], jx);
+                jy = __builtin_fma(fi, a.k.vy[i], jy);
+                E = __builtin_fma(fi, a.k.hv2[i], E);
             }
         }
         const CellEq c = cell_eq_from_sums(r, jx, jy, E);
@@ -237,88 +389,40 @@ __global__ __launch_bounds__(64 * NW) void k_step(StepArgs a)
         uxt[m] = c.uxt;
         uyt[m] = c.uyt;
         t0[m] = c.t0;
-        if (act) {
+        if (act && grp == 0) {
             const double uy = jy / r;
             const double e = 0.5 * r * uy * uy;
             ke_s += e;
             ke_m = fmax(ke_m, e);
             // rest particle: no convection, f^eq_0 = rho F_0 (1 - u^2/2T)
-            const double F0 = 1.0 - 6.0 * (weight_k(M, 0, c.T) + weight_k(M, 1, c.T) +
-                                            weight_k(M, 2, c.T));
+            const double F0 = 1.0 - 6.0 * (weight_c(a.k, 0, c.T) + weight_c(a.k, 1, c.T) +
+                                            weight_c(a.k, 2, c.T));
             const double fe = c.rho * F0 * c.t0;
             a.fout[(int64_t)gy * a.nx + gx] = __builtin_fma(-a.ct, fz - fe, fz);
         }
     }
-    if (a.ke_part) {
+    if (a.ke_part && grp == 0) {
         ke_s = wave_sum(ke_s);
         ke_m = wave_max(ke_m);
         if (lane == 0) {
-            s_red[2 * w] = ke_s;
-            s_red[2 * w + 1] = ke_m;
+            a.ke_part[2 * tile] = ke_s;
+            a.ke_part[2 * tile + 1] = ke_m;
         }
     }
 
-    // ---- phase 2: the 18 moving velocities ----
-    double pre[NPRE];
-    stage_load<TY, NT, NPRE>(a, 1, x0, y0, interior, plane, pre);
-    double A[R];
-#pragma unroll 1
-    for (int i = 1; i < NV; ++i) {
-        const int k = (i - 1) / 6;
-        if (i == 1 || i == 7 || i == 13) {
-#pragma unroll
-            for (int m = 0; m < R; ++m) A[m] = rho[m] * weight_k(M, k, Tm[m]);
-        }
-        stage_store<TY, NT, NPRE>(s_pl, pre);
-        __syncthreads();
-        if (i == 1 && a.ke_part && threadIdx.x == 0) {
-            double s = 0.0, mx = 0.0;
-            for (int q = 0; q < NW; ++q) {
-                s += s_red[2 * q];
-                mx = fmax(mx, s_red[2 * q + 1]);
-            }
-            a.ke_part[2 * tile] = s;
-            a.ke_part[2 * tile + 1] = mx;
-        }
-        if (i + 1 < NV) stage_load<TY, NT, NPRE>(a, i + 1, x0, y0, interior, plane, pre);
-
-        const double vx = M->vx[i], vy = M->vy[i], eps = M->eps;
-        if (vx < 0.0)
-            x_pass<R, true>(s_pl, s_dx, w, lane, vx, eps);
-        else
-            x_pass<R, false>(s_pl, s_dx, w, lane, vx, eps);
-        double dhy[R], fc[R];
-        if (vy > 0.0) {
-            y_pass<R, false>(s_pl, w, lane, vy, eps, dhy, fc);
-        } else if (vy < 0.0) {
-            y_pass<R, true>(s_pl, w, lane, vy, eps, dhy, fc);
-        } else {
-#pragma unroll
-            for (int m = 0; m < R; ++m) {
-                fc[m] = s_pl[(w * R + m + HALO) * PITCH + lane + HALO];
-                dhy[m] = 0.0;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < R; ++m) {
-            const int gy = y0 + w * R + m;
-            const double dhx = s_dx[(w * R + m) * XPITCH + lane];
-            const double eta = __builtin_fma(vx, uxt[m], vy * uyt[m]);
-            const double fe = A[m] * feq_poly(eta, t0[m]);
-            double fn = __builtin_fma(-a.cx, dhx, fc[m]);
-            fn = __builtin_fma(-a.cy, dhy[m], fn);
-            fn = __builtin_fma(-a.ct, fc[m] - fe, fn);
-            if (gx < a.nx && gy < a.ny) a.fout[i * plane + (int64_t)gy * a.nx + gx] = fn;
-        }
-    }
+    // ---- phase 2 ----
+    const TileMap t = tile_map<R>(a, x0, y0, lane, !interior);
+    if (interior)
+        plane_loop<R, G, false>(a, grp, x0, y0, lane, t, plane, s_pl, s_dx, rho, Tm, uxt, uyt, t0);
+    else
+        plane_loop<R, G, true>(a, grp, x0, y0, lane, t, plane, s_pl, s_dx, rho, Tm, uxt, uyt, t0);
 }
 
 // ---------------------------------------------------------------------------
 // f = f^eq(rho, u, T), one thread per cell (Eq. (28)).
 __global__ void k_init(const double* __restrict__ rho, const double* __restrict__ ux,
                        const double* __restrict__ uy, const double* __restrict__ T,
-                       double* __restrict__ f, const Model* __restrict__ M, int64_t n)
+                       double* __restrict__ f, int64_t n, Consts k)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
@@ -327,20 +431,20 @@ __global__ void k_init(const double* __restrict__ rho, const double* __restrict_
     const double t0 = 1.0 - (u * u + v * v) / (2.0 * t);
     const double uxt = u * iT, uyt = v * iT;
     double A[4];
-    A[1] = r * weight_k(M, 0, t);
-    A[2] = r * weight_k(M, 1, t);
-    A[3] = r * weight_k(M, 2, t);
-    A[0] = r * (1.0 - 6.0 * (weight_k(M, 0, t) + weight_k(M, 1, t) + weight_k(M, 2, t)));
+    A[1] = r * weight_c(k, 0, t);
+    A[2] = r * weight_c(k, 1, t);
+    A[3] = r * weight_c(k, 2, t);
+    A[0] = r * (1.0 - 6.0 * (weight_c(k, 0, t) + weight_c(k, 1, t) + weight_c(k, 2, t)));
     f[c] = A[0] * t0;
 #pragma unroll
     for (int i = 1; i < NV; ++i) {
-        const double eta = __builtin_fma(M->vx[i], uxt, M->vy[i] * uyt);
+        const double eta = __builtin_fma(k.vx[i], uxt, k.vy[i] * uyt);
         f[i * n + c] = A[1 + (i - 1) / 6] * feq_poly(eta, t0);
     }
 }
 
-// Fixed-side equilibria: four (rho, ux, uy, T) states -> M->side_eq.
-__global__ void k_side_eq(Model* M, double4 s0, double4 s1, double4 s2, double4 s3)
+// Fixed-side equilibria: four (rho, ux, uy, T) states -> out[4][19].
+__global__ void k_side_eq(double* out, double4 s0, double4 s1, double4 s2, double4 s3, Consts k)
 {
     const int i = threadIdx.x;
     const int s = blockIdx.x;
@@ -348,24 +452,24 @@ __global__ void k_side_eq(Model* M, double4 s0, double4 s1, double4 s2, double4 
     const double4 st = s == 0 ? s0 : s == 1 ? s1 : s == 2 ? s2 : s3;
     const double r = st.x, u = st.y, v = st.z, t = st.w;
     if (!(r > 0.0) || !(t > 0.0)) {
-        M->side_eq[s][i] = 0.0;
+        out[s * NV + i] = 0.0;
         return;
     }
     const double iT = 1.0 / t;
     const double t0 = 1.0 - (u * u + v * v) / (2.0 * t);
     double A;
     if (i == 0)
-        A = r * (1.0 - 6.0 * (weight_k(M, 0, t) + weight_k(M, 1, t) + weight_k(M, 2, t)));
+        A = r * (1.0 - 6.0 * (weight_c(k, 0, t) + weight_c(k, 1, t) + weight_c(k, 2, t)));
     else
-        A = r * weight_k(M, (i - 1) / 6, t);
-    const double eta = __builtin_fma(M->vx[i], u * iT, M->vy[i] * (v * iT));
-    M->side_eq[s][i] = A * feq_poly(eta, t0);
+        A = r * weight_c(k, (i - 1) / 6, t);
+    const double eta = __builtin_fma(k.vx[i], u * iT, k.vy[i] * (v * iT));
+    out[s * NV + i] = A * feq_poly(eta, t0);
 }
 
 // Moments of Eq. (10) per cell.
 __global__ void k_moments(const double* __restrict__ f, double* __restrict__ rho,
                           double* __restrict__ ux, double* __restrict__ uy,
-                          double* __restrict__ T, const Model* __restrict__ M, int64_t n)
+                          double* __restrict__ T, int64_t n, Consts k)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
@@ -374,9 +478,9 @@ __global__ void k_moments(const double* __restrict__ f, double* __restrict__ rho
     for (int i = 0; i < NV; ++i) {
         const double fi = f[i * n + c];
         r += fi;
-        jx = __builtin_fma(fi, M->vx[i], jx);
-        jy = __builtin_fma(fi, M->vy[i], jy);
-        E = __builtin_fma(fi, M->hv2[i], E);
+        jx = __builtin_fma(fi, k.vx[i], jx);
+        jy = __builtin_fma(fi, k.vy[i], jy);
+        E = __builtin_fma(fi, k.hv2[i], E);
     }
     const double u = jx / r, v = jy / r;
     rho[c] = r;
@@ -386,9 +490,8 @@ __global__ void k_moments(const double* __restrict__ f, double* __restrict__ rho
 }
 
 // Transverse kinetic energy partials: one (sum, max) pair per block of 256 cells.
-__global__ __launch_bounds__(256) void k_kinetic_part(const double* __restrict__ f,
-                                                      const Model* __restrict__ M, int64_t n,
-                                                      double* __restrict__ part)
+__global__ __launch_bounds__(256) void k_kinetic_part(const double* __restrict__ f, int64_t n,
+                                                      double* __restrict__ part, Consts k)
 {
     __shared__ double sr[8];
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -399,7 +502,7 @@ __global__ __launch_bounds__(256) void k_kinetic_part(const double* __restrict__
         for (int i = 0; i < NV; ++i) {
             const double fi = f[i * n + c];
             r += fi;
-            jy = __builtin_fma(fi, M->vy[i], jy);
+            jy = __builtin_fma(fi, k.vy[i], jy);
         }
         const double uy = jy / r;
         e = 0.5 * r * uy * uy;
@@ -443,65 +546,59 @@ __global__ __launch_bounds__(256) void k_reduce_pairs(const double* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Launch table of the step kernel variants (rows per lane R, waves per
-// workgroup NW).
+// Step kernel variants: rows per lane R, velocity groups G, and the
+// wavefronts-per-SIMD target W that bounds the register budget.
 struct StepVariant {
-    int R, NW;
+    int R, G, W;
     void (*kernel)(StepArgs);
 };
 
 static const StepVariant kStepVariants[] = {
-    {4, 4, k_step<4, 4>},
-    {8, 4, k_step<8, 4>},
-    {8, 2, k_step<8, 2>},
-    {4, 8, k_step<4, 8>},
-    {2, 8, k_step<2, 8>},
+    {8, 1, 2, k_step<8, 1, 2>}, {8, 3, 2, k_step<8, 3, 2>}, {4, 1, 3, k_step<4, 1, 3>},
+    {4, 3, 3, k_step<4, 3, 3>}, {4, 2, 3, k_step<4, 2, 3>}, {8, 1, 3, k_step<8, 1, 3>},
+    {2, 3, 4, k_step<2, 3, 4>}, {2, 6, 4, k_step<2, 6, 4>}, {8, 2, 2, k_step<8, 2, 2>},
+    {4, 6, 3, k_step<4, 6, 3>},
 };
 constexpr int kNumStepVariants = sizeof(kStepVariants) / sizeof(kStepVariants[0]);
 
 int step_variant_count() { return kNumStepVariants; }
-int step_variant_rows(int v) { return kStepVariants[v].R * kStepVariants[v].NW; }
-int step_variant_desc(int v, int* R, int* NW)
+int step_variant_desc(int v, int* R, int* G, int* W)
 {
     if (v < 0 || v >= kNumStepVariants) return -1;
     *R = kStepVariants[v].R;
-    *NW = kStepVariants[v].NW;
+    *G = kStepVariants[v].G;
+    *W = kStepVariants[v].W;
     return 0;
-}
-
-hipError_t launch_step(int variant, const double* fin, double* fout, const Model* M,
-                       double* ke_part, int nx, int ny, const int bc[4], double cx, double cy,
-                       double ct, hipStream_t st)
-{
-    const StepVariant& V = kStepVariants[variant];
-    const int TY = V.R * V.NW;
-    StepArgs a;
-    a.fin = fin;
-    a.fout = fout;
-    a.M = M;
-    a.ke_part = ke_part;
-    a.nx = nx;
-    a.ny = ny;
-    a.bc0 = bc[0];
-    a.bc1 = bc[1];
-    a.bc2 = bc[2];
-    a.bc3 = bc[3];
-    a.tiles_x = (nx + TX - 1) / TX;
-    const int tiles_y = (ny + TY - 1) / TY;
-    a.ntiles = a.tiles_x * tiles_y;
-    a.per_xcd = (a.ntiles + 7) / 8;
-    a.cx = cx;
-    a.cy = cy;
-    a.ct = ct;
-    hipLaunchKernelGGL(V.kernel, dim3(8 * a.per_xcd), dim3(64 * V.NW), 0, st, a);
-    return hipGetLastError();
 }
 
 int step_ntiles(int variant, int nx, int ny)
 {
     const StepVariant& V = kStepVariants[variant];
-    const int TY = V.R * V.NW;
-    return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY);
+    return ((nx + TX - 1) / TX) * ((ny + V.R - 1) / V.R);
+}
+
+hipError_t launch_step(int variant, const double* fin, double* fout, const Consts& k,
+                       double* ke_part, int nx, int ny, const int bc[4], double cx, double cy,
+                       double ct, hipStream_t st)
+{
+    const StepVariant& V = kStepVariants[variant];
+    StepArgs a;
+    a.fin = fin;
+    a.fout = fout;
+    a.ke_part = ke_part;
+    a.nx = nx;
+    a.ny = ny;
+    for (int s = 0; s < 4; ++s) a.bc[s] = bc[s];
+    a.tiles_x = (nx + TX - 1) / TX;
+    a.ntiles = a.tiles_x * ((ny + V.R - 1) / V.R);
+    a.nwork = a.ntiles * V.G;
+    a.per_xcd = (a.nwork + 7) / 8;
+    a.cx = cx;
+    a.cy = cy;
+    a.ct = ct;
+    a.k = k;
+    hipLaunchKernelGGL(V.kernel, dim3(8 * a.per_xcd), dim3(64), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce_pairs(const double* part, int n, double dxdy, double* out2,
@@ -512,36 +609,36 @@ hipError_t launch_reduce_pairs(const double* part, int n, double dxdy, double* o
 }
 
 hipError_t launch_init(const double* rho, const double* ux, const double* uy, const double* T,
-                       double* f, const Model* M, int64_t n, hipStream_t st)
+                       double* f, const Consts& k, int64_t n, hipStream_t st)
 {
     const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(k_init, dim3((unsigned)blocks), dim3(256), 0, st, rho, ux, uy, T, f, M, n);
+    hipLaunchKernelGGL(k_init, dim3((unsigned)blocks), dim3(256), 0, st, rho, ux, uy, T, f, n, k);
     return hipGetLastError();
 }
 
-hipError_t launch_side_eq(Model* M, const double s[4][4], hipStream_t st)
+hipError_t launch_side_eq(double* out, const double s[4][4], const Consts& k, hipStream_t st)
 {
     double4 q[4];
-    for (int k = 0; k < 4; ++k) q[k] = make_double4(s[k][0], s[k][1], s[k][2], s[k][3]);
-    hipLaunchKernelGGL(k_side_eq, dim3(4), dim3(32), 0, st, M, q[0], q[1], q[2], q[3]);
+    for (int j = 0; j < 4; ++j) q[j] = make_double4(s[j][0], s[j][1], s[j][2], s[j][3]);
+    hipLaunchKernelGGL(k_side_eq, dim3(4), dim3(32), 0, st, out, q[0], q[1], q[2], q[3], k);
     return hipGetLastError();
 }
 
 hipError_t launch_moments(const double* f, double* rho, double* ux, double* uy, double* T,
-                          const Model* M, int64_t n, hipStream_t st)
+                          const Consts& k, int64_t n, hipStream_t st)
 {
     const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(k_moments, dim3((unsigned)blocks), dim3(256), 0, st, f, rho, ux, uy, T, M,
-                       n);
+    hipLaunchKernelGGL(k_moments, dim3((unsigned)blocks), dim3(256), 0, st, f, rho, ux, uy, T, n,
+                       k);
     return hipGetLastError();
 }
 
-hipError_t launch_kinetic_part(const double* f, const Model* M, int64_t n, double* part,
+hipError_t launch_kinetic_part(const double* f, const Consts& k, int64_t n, double* part,
                                int* nparts, hipStream_t st)
 {
     const int64_t blocks = (n + 255) / 256;
     *nparts = (int)blocks;
-    hipLaunchKernelGGL(k_kinetic_part, dim3((unsigned)blocks), dim3(256), 0, st, f, M, n, part);
+    hipLaunchKernelGGL(k_kinetic_part, dim3((unsigned)blocks), dim3(256), 0, st, f, n, part, k);
     return hipGetLastError();
 }
 

@@ -13,30 +13,29 @@ struct lbm_ctx {
     int device = 0;
     int variant = 0;
     int ke_cap = 0;
-    lbmd::Model* model = nullptr;  // device copy of the per-context constants
+    lbmd::Consts k;                // per-context constants (kernel arguments)
     double* scratch = nullptr;     // 19 planes: ping-pong state of multi-step calls
     double* ke_part = nullptr;     // [ke_cap][2] diagnostic partials
 };
 
 int lbmi_validate(const lbm_params* p);
-void lbmi_fill_model(const lbm_params* p, lbmd::Model* h);
+void lbmi_fill_consts(const lbm_params* p, lbmd::Consts* h);
 int lbmi_default_variant(int nx, int ny);
 
 namespace lbmd {
 int step_variant_count();
-int step_variant_rows(int v);
-int step_variant_desc(int v, int* R, int* NW);
+int step_variant_desc(int v, int* R, int* G, int* W);
 int step_ntiles(int variant, int nx, int ny);
-hipError_t launch_step(int variant, const double* fin, double* fout, const Model* M,
+hipError_t launch_step(int variant, const double* fin, double* fout, const Consts& k,
                        double* ke_part, int nx, int ny, const int bc[4], double cx, double cy,
                        double ct, hipStream_t st);
 hipError_t launch_reduce_pairs(const double* part, int n, double dxdy, double* out2,
                                hipStream_t st);
 hipError_t launch_init(const double* rho, const double* ux, const double* uy, const double* T,
-                       double* f, const Model* M, int64_t n, hipStream_t st);
-hipError_t launch_side_eq(Model* M, const double s[4][4], hipStream_t st);
+                       double* f, const Consts& k, int64_t n, hipStream_t st);
+hipError_t launch_side_eq(double* out, const double s[4][4], const Consts& k, hipStream_t st);
 hipError_t launch_moments(const double* f, double* rho, double* ux, double* uy, double* T,
-                          const Model* M, int64_t n, hipStream_t st);
-hipError_t launch_kinetic_part(const double* f, const Model* M, int64_t n, double* part,
+                          const Consts& k, int64_t n, hipStream_t st);
+hipError_t launch_kinetic_part(const double* f, const Consts& k, int64_t n, double* part,
                                int* nparts, hipStream_t st);
 }  // namespace lbmd
