@@ -109,14 +109,16 @@ int lbm_moments(lbm_ctx* ctx, const double* f, double* rho, double* ux, double* 
  * rho u_y^2 / 2 of f (device double[2]). */
 int lbm_kinetic_y(lbm_ctx* ctx, const double* f, double* out2, lbm_stream stream);
 
-/* Step-kernel variants for the autotuner. A variant is (R, G, W): one-wavefront
- * workgroups own tiles of 64 x R cells and one of G groups of the 18 moving
- * velocities; W is the wavefronts-per-SIMD target that bounds the register
- * budget. Every variant computes the same result; they differ in speed only.
- * lbm_set_step_variant selects the variant later lbm_step calls launch. */
+/* Step-kernel variants for the autotuner. lbm_step_variant_info fills
+ * info5[0..4] = (R, G, W, D, NT): one-wavefront workgroups own tiles of
+ * 64 x R cells and one of G groups of the 18 moving velocities; W is the
+ * wavefronts-per-SIMD target that bounds the register budget; D planes are
+ * prefetched ahead of the one being computed; NT = 1 stores f^{n+1} with
+ * non-temporal stores. Every variant computes the same result; they differ in
+ * speed only. lbm_set_step_variant selects the variant that later lbm_step
+ * calls of that context launch. */
 int lbm_step_variant_count(void);
-int lbm_step_variant_info(int32_t variant, int32_t* rows_per_lane, int32_t* groups,
-                          int32_t* waves_per_simd);
+int lbm_step_variant_info(int32_t variant, int32_t* info5);
 int lbm_set_step_variant(lbm_ctx* ctx, int32_t variant);
 int lbm_get_step_variant(lbm_ctx* ctx, int32_t* variant);
 

@@ -222,15 +222,16 @@ int lbm_kinetic_y(lbm_ctx* c, const double* f, double* out2, lbm_stream stream)
 
 int lbm_step_variant_count(void) { return step_variant_count(); }
 
-int lbm_step_variant_info(int32_t v, int32_t* rows_per_lane, int32_t* groups,
-                          int32_t* waves_per_simd)
+int lbm_step_variant_info(int32_t v, int32_t* info5)
 {
-    int R = 0, G = 0, W = 0;
-    if (!rows_per_lane || !groups || !waves_per_simd || step_variant_desc(v, &R, &G, &W))
+    int R = 0, G = 0, W = 0, D = 0, NT = 0;
+    if (!info5 || step_variant_desc(v, &R, &G, &W, &D, &NT))
         return fail(LBM_EINVAL, "bad variant%s%lld");
-    *rows_per_lane = R;
-    *groups = G;
-    *waves_per_simd = W;
+    info5[0] = R;
+    info5[1] = G;
+    info5[2] = W;
+    info5[3] = D;
+    info5[4] = NT;
     return LBM_OK;
 }
 
@@ -248,18 +249,21 @@ int lbm_get_step_variant(lbm_ctx* c, int32_t* v)
     return LBM_OK;
 }
 
-// Default step variant: enough workgroups to cover the 256 CUs several times
-// over, with the longest strips (fewest redundant faces) that allows.
+// Default step variant (the autotuner can override it per context): on large
+// grids one velocity group with two planes in flight and non-temporal
+// stores; on small grids three velocity groups, so that there are enough
+// workgroups for all 256 CUs.
 int lbmi_default_variant(int nx, int ny)
 {
     const long long cells = (long long)nx * ny;
-    int want_R = cells >= (1ll << 21) ? 8 : 4;
-    int want_G = cells >= (1ll << 21) ? 1 : 3;
-    if (ny < 8) want_R = 2;
+    const int want[5] = {4, cells >= (1ll << 21) ? 1 : 3, 3, cells >= (1ll << 21) ? 2 : 1,
+                         cells >= (1ll << 21) ? 1 : 0};
     for (int v = 0; v < step_variant_count(); ++v) {
-        int R = 0, G = 0, W = 0;
-        step_variant_desc(v, &R, &G, &W);
-        if (R == want_R && G == want_G) return v;
+        int d[5];
+        step_variant_desc(v, &d[0], &d[1], &d[2], &d[3], &d[4]);
+        if (d[0] == want[0] && d[1] == want[1] && d[2] == want[2] && d[3] == want[3] &&
+            d[4] == want[4])
+            return v;
     }
     return 0;
 }

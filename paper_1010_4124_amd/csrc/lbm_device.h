@@ -82,18 +82,15 @@ __device__ __forceinline__ double feq_poly(double eta, double t0)
     return __builtin_fma(eta, in, t0);
 }
 
-// n / d for the WENO normalisation: hardware reciprocal, two Newton steps and
-// one residual correction (d is positive and far from the denormal and
-// overflow ranges there).
+// n / d for the WENO normalisation: the hardware reciprocal (relative error
+// below 2^-24) and one residual correction, which leaves a relative error of
+// order 1e-15 on the quotient; d is positive and far from the denormal and
+// overflow ranges there.
 __device__ __forceinline__ double div_nr(double n, double d)
 {
-    double r = __builtin_amdgcn_rcp(d);
-    double e = __builtin_fma(-d, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-d, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    double q = n * r;
-    double res = __builtin_fma(-d, q, n);
+    const double r = __builtin_amdgcn_rcp(d);
+    const double q = n * r;
+    const double res = __builtin_fma(-d, q, n);
     return __builtin_fma(res, r, q);
 }
 
@@ -106,45 +103,74 @@ __device__ __forceinline__ double div_nr(double n, double d)
 // The arithmetic is that of Eqs. (48)-(55) regrouped so that the first and
 // second differences of the samples are shared by the faces of the strip:
 // with g_k = P_{k+1} - P_k and D_k = g_{k+1} - g_k,
-//   sigma_1 = 13/12 D_j^2   + (D_j / 2 + g_{j+1})^2,
-//   sigma_2 = 13/12 D_j+1^2 + ((g_{j+1} + g_{j+2}) / 2)^2,
-//   sigma_3 = 13/12 D_j+2^2 + (D_{j+2} / 2 - g_{j+2})^2,
+//   eps + sigma_1 = E_j     + (D_j / 2 + g_{j+1})^2,
+//   eps + sigma_2 = E_{j+1} + ((g_{j+1} + g_{j+2}) / 2)^2,
+//   eps + sigma_3 = E_{j+2} + (D_{j+2} / 2 - g_{j+2})^2,   E_k = 13/12 D_k^2 + eps,
 // h^q = c + r_q with r_1 = 5/6 g_{j+1} - 1/3 g_j, r_2 = 1/6 g_{j+1} + 1/3 g_{j+2},
 // r_3 = 2/3 g_{j+2} - 1/6 g_{j+3}, and the weights delta_q / (eps+sigma_q)^2
 // scaled by prod_p (eps+sigma_p)^2 / delta_1, so that one division per face
-// remains.
-template <int R>
-__device__ __forceinline__ void weno_faces(const double (&P)[R + 5], double eps, double (&hq)[R + 1])
+// remains. The differences are formed in a window that slides along the
+// strip, which keeps few values live at a time.
+template <int R, class OnFace>
+__device__ __forceinline__ void weno_faces(const double (&P)[R + 5], double eps, OnFace&& on_face)
 {
-    double g[R + 4], D[R + 3], E[R + 3];
-#pragma unroll
-    for (int k = 0; k < R + 4; ++k) g[k] = P[k + 1] - P[k];
-#pragma unroll
-    for (int k = 0; k < R + 3; ++k) {
-        D[k] = g[k + 1] - g[k];
-        E[k] = (13.0 / 12.0) * D[k] * D[k];
-    }
+    constexpr double C13 = 13.0 / 12.0;
+    double g0 = P[1] - P[0], g1 = P[2] - P[1], g2 = P[3] - P[2], g3 = P[4] - P[3];
+    double D0 = g1 - g0, D1 = g2 - g1, D2 = g3 - g2;
+    double E0 = __builtin_fma(C13 * D0, D0, eps);
+    double E1 = __builtin_fma(C13 * D1, D1, eps);
+    double E2 = __builtin_fma(C13 * D2, D2, eps);
 #pragma unroll
     for (int j = 0; j <= R; ++j) {
-        const double b1 = __builtin_fma(0.5, D[j], g[j + 1]);
-        const double b2 = 0.5 * (g[j + 1] + g[j + 2]);
-        const double b3 = __builtin_fma(0.5, D[j + 2], -g[j + 2]);
-        double q1 = eps + __builtin_fma(b1, b1, E[j]);
-        double q2 = eps + __builtin_fma(b2, b2, E[j + 1]);
-        double q3 = eps + __builtin_fma(b3, b3, E[j + 2]);
+        const double b1 = __builtin_fma(0.5, D0, g1);
+        const double b2 = 0.5 * (g1 + g2);
+        const double b3 = __builtin_fma(0.5, D2, -g2);
+        double q1 = __builtin_fma(b1, b1, E0);
+        double q2 = __builtin_fma(b2, b2, E1);
+        double q3 = __builtin_fma(b3, b3, E2);
         q1 *= q1;
         q2 *= q2;
         q3 *= q3;
         const double W1 = q2 * q3;
         const double W2 = 6.0 * (q1 * q3);
         const double W3 = 3.0 * (q1 * q2);
-        const double r1 = __builtin_fma(5.0 / 6.0, g[j + 1], -(1.0 / 3.0) * g[j]);
-        const double r2 = __builtin_fma(1.0 / 3.0, g[j + 2], (1.0 / 6.0) * g[j + 1]);
-        const double r3 = __builtin_fma(2.0 / 3.0, g[j + 2], -(1.0 / 6.0) * g[j + 3]);
+        const double r1 = __builtin_fma(5.0 / 6.0, g1, -(1.0 / 3.0) * g0);
+        const double r2 = __builtin_fma(1.0 / 3.0, g2, (1.0 / 6.0) * g1);
+        const double r3 = __builtin_fma(2.0 / 3.0, g2, -(1.0 / 6.0) * g3);
         const double num = __builtin_fma(W1, r1, __builtin_fma(W2, r2, W3 * r3));
         const double den = W1 + W2 + W3;
-        hq[j] = P[j + 2] + div_nr(num, den);
+        on_face(j, P[j + 2] + div_nr(num, den));
+        if (j < R) {
+            g0 = g1;
+            g1 = g2;
+            g2 = g3;
+            g3 = P[j + 5] - P[j + 4];
+            D0 = D1;
+            D1 = D2;
+            D2 = g3 - g2;
+            E0 = E1;
+            E1 = E2;
+            E2 = __builtin_fma(C13 * D2, D2, eps);
+        }
     }
+}
+
+// Flux differences of an R-cell strip as the faces of weno_faces complete:
+// on_cell(m, h_{m+1/2} - h_{m-1/2}) for strip cell m in natural order, where
+// NEG says the samples were passed reversed (v < 0).
+template <int R, bool NEG, class OnCell>
+__device__ __forceinline__ void weno_strip(const double (&P)[R + 5], double eps, OnCell&& on_cell)
+{
+    double hp = 0.0;
+    weno_faces<R>(P, eps, [&](int j, double h) {
+        if (j > 0) {
+            if (NEG)
+                on_cell(R - j, hp - h);
+            else
+                on_cell(j - 1, h - hp);
+        }
+        hp = h;
+    });
 }
 
 __host__ __device__ __forceinline__ int wrap_index(int g, int n)

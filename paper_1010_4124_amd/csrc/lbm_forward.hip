@@ -163,11 +163,15 @@ __device__ __forceinline__ void stage_load(const StepArgs& a, int i, int x0, int
                                            double (&pre)[Stage<R>::NPRE])
 {
     if (!BND) {
-        const double* base = a.fin + i * plane + (int64_t)(y0 - HALO) * a.nx + x0;
+        const unsigned ul = (unsigned)lane;
 #pragma unroll
-        for (int r = 0; r < Stage<R>::ROWS; ++r) pre[r] = base[(int64_t)r * a.nx + lane];
-        const double* hb = a.fin + i * plane + (int64_t)y0 * a.nx + x0;
-        pre[Stage<R>::ROWS] = hb[t.hrow * a.nx + t.hlx];
+        for (int r = 0; r < Stage<R>::ROWS; ++r) {
+            const double* row = a.fin + i * plane + (int64_t)(y0 - HALO + r) * a.nx + x0;
+            pre[r] = row[ul];
+        }
+        // halo columns: offset from column x0 - 3 so that it is never negative
+        const double* hb = a.fin + i * plane + (int64_t)y0 * a.nx + x0 - HALO;
+        pre[Stage<R>::ROWS] = hb[(unsigned)(t.hrow * a.nx + t.hlx + HALO)];
     } else {
         const int64_t pi = i * plane, px = a.k.mirx[i] * plane, py = a.k.miry[i] * plane;
 #pragma unroll
@@ -225,7 +229,8 @@ __device__ __forceinline__ void stage_store(const StepArgs& a, int i, int y0, in
     s_pl[slot] = h;
 }
 
-// x pass: lane -> (row r = lane % R, strip s = lane / R).
+// x pass: lane -> (row r = lane % R, strip s = lane / R); the flux
+// differences go to s_dx.
 template <int R, bool NEG>
 __device__ __forceinline__ void x_pass(const double* s_pl, double* s_dx, int lane, double v,
                                        double eps)
@@ -235,31 +240,21 @@ __device__ __forceinline__ void x_pass(const double* s_pl, double* s_dx, int lan
     double P[R + 5];
 #pragma unroll
     for (int k = 0; k < R + 5; ++k) P[k] = v * (NEG ? b[R + 5 - k] : b[k]);
-    double hq[R + 1];
-    weno_faces<R>(P, eps, hq);
     double* out = s_dx + r * XPITCH + s * R;
-#pragma unroll
-    for (int m = 0; m < R; ++m) out[m] = NEG ? (hq[R - m - 1] - hq[R - m]) : (hq[m + 1] - hq[m]);
+    weno_strip<R, NEG>(P, eps, [&](int m, double d) { out[m] = d; });
 }
 
-// y pass: lane = column; also returns the centre values of the strip.
-template <int R, bool NEG>
-__device__ __forceinline__ void y_pass(const double* s_pl, int lane, double v, double eps,
-                                       double (&dhy)[R], double (&fc)[R])
+// y pass: lane = column; calls upd(m, f_m, dh^y_m) for each cell of the strip
+// as soon as its two faces are known.
+template <int R, bool NEG, class Upd>
+__device__ __forceinline__ void y_pass(const double* s_pl, int lane, double v, double eps, Upd&& upd)
 {
     const double* col = s_pl + lane + HALO;
-    double fw[R + 5];
-#pragma unroll
-    for (int k = 0; k < R + 5; ++k) fw[k] = NEG ? col[(R + 5 - k) * PITCH] : col[k * PITCH];
-#pragma unroll
-    for (int m = 0; m < R; ++m) fc[m] = NEG ? fw[R + 2 - m] : fw[m + 3];
     double P[R + 5];
 #pragma unroll
-    for (int k = 0; k < R + 5; ++k) P[k] = v * fw[k];
-    double hq[R + 1];
-    weno_faces<R>(P, eps, hq);
-#pragma unroll
-    for (int m = 0; m < R; ++m) dhy[m] = NEG ? (hq[R - m - 1] - hq[R - m]) : (hq[m + 1] - hq[m]);
+    for (int k = 0; k < R + 5; ++k) P[k] = v * (NEG ? col[(R + 5 - k) * PITCH] : col[k * PITCH]);
+    // the centre value of cell m is re-read from LDS when the cell completes
+    weno_strip<R, NEG>(P, eps, [&](int m, double d) { upd(m, col[(m + HALO) * PITCH], d); });
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -278,7 +273,11 @@ __device__ __forceinline__ double wave_max(double v)
 // Phase 2 of one tile: this group's moving velocities. Instantiated once for
 // interior tiles and once for boundary tiles, so that each loop is straight
 // line code and the compiler tracks its outstanding loads and stores exactly.
-template <int R, int G, bool BND>
+// DEPTH planes are in flight ahead of the one being computed; every load is
+// issued unconditionally (past the group's last plane the last plane is
+// re-read) and consumed after the current plane's stores, so waiting for a
+// staged plane never waits for stores.
+template <int R, int G, bool BND, int DEPTH, bool NT>
 __device__ __forceinline__ void plane_loop(const StepArgs& a, int grp, int x0, int y0, int lane,
                                            const TileMap& t, int64_t plane, double* s_pl,
                                            double* s_dx, const double (&rho)[R],
@@ -286,64 +285,79 @@ __device__ __forceinline__ void plane_loop(const StepArgs& a, int grp, int x0, i
                                            const double (&uyt)[R], const double (&t0)[R])
 {
     constexpr int NPL = 18 / G;  // moving velocities per group
+    static_assert(DEPTH == 1 || NPL % 2 == 0, "two-deep pipeline needs an even plane count");
     const int gx = x0 + lane;
-    const int i0 = 1 + grp * NPL;
-    double pre[Stage<R>::NPRE];
-    stage_load<R, BND>(a, i0, x0, y0, lane, t, plane, pre);
-    stage_store<R, BND>(a, i0, y0, lane, t, s_pl, pre);
-    __syncthreads();
-    double A[R];
+    const int i0 = 1 + grp * NPL, iend = i0 + NPL;
+    double A[R];  // (dt/tau) rho F_k(T) of the current speed shell
     int kcur = -1;
-    // Each iteration computes the plane already in LDS. The next plane's loads
-    // are issued first (unconditionally: the last iteration re-reads its own
-    // plane) and consumed only after this plane's stores, all inside one
-    // iteration, so waiting for them never waits for the stores.
-#pragma unroll 1
-    for (int i = i0; i < i0 + NPL; ++i) {
+    const double omct = 1.0 - a.ct;
+
+    // f' = f - cx dh^x - cy dh^y - ct (f - f^eq)
+    //    = (1 - ct) f + (ct rho F_k) poly(eta) - cx dh^x - cy dh^y
+    auto compute = [&](int i) {
         const int k = (i - 1) / 6;
         if (k != kcur) {
             kcur = k;
 #pragma unroll
-            for (int m = 0; m < R; ++m) A[m] = rho[m] * weight_c(a.k, k, Tm[m]);
+            for (int m = 0; m < R; ++m) A[m] = (a.ct * rho[m]) * weight_c(a.k, k, Tm[m]);
         }
-        const int inext = i + 1 < i0 + NPL ? i + 1 : i;
-        stage_load<R, BND>(a, inext, x0, y0, lane, t, plane, pre);
-
         const double vx = a.k.vx[i], vy = a.k.vy[i], eps = a.k.eps;
         if (vx < 0.0)
             x_pass<R, true>(s_pl, s_dx, lane, vx, eps);
         else
             x_pass<R, false>(s_pl, s_dx, lane, vx, eps);
-        double dhy[R], fc[R];
-        if (vy > 0.0) {
-            y_pass<R, false>(s_pl, lane, vy, eps, dhy, fc);
-        } else if (vy < 0.0) {
-            y_pass<R, true>(s_pl, lane, vy, eps, dhy, fc);
-        } else {
-#pragma unroll
-            for (int m = 0; m < R; ++m) {
-                fc[m] = s_pl[(m + HALO) * PITCH + lane + HALO];
-                dhy[m] = 0.0;
-            }
-        }
         __syncthreads();
-        double* dst = a.fout + i * plane + (int64_t)y0 * a.nx + gx;
-#pragma unroll
-        for (int m = 0; m < R; ++m) {
+        double* base = a.fout + i * plane + (int64_t)y0 * a.nx + x0;
+        auto upd = [&](int m, double fcm, double dhy) {
             const double dhx = s_dx[m * XPITCH + lane];
             const double eta = __builtin_fma(vx, uxt[m], vy * uyt[m]);
-            const double fe = A[m] * feq_poly(eta, t0[m]);
-            double fn = __builtin_fma(-a.cx, dhx, fc[m]);
-            fn = __builtin_fma(-a.cy, dhy[m], fn);
-            fn = __builtin_fma(-a.ct, fc[m] - fe, fn);
-            if (!BND || (gx < a.nx && y0 + m < a.ny)) dst[(int64_t)m * a.nx] = fn;
+            double fn = __builtin_fma(omct, fcm, A[m] * feq_poly(eta, t0[m]));
+            fn = __builtin_fma(-a.cx, dhx, fn);
+            fn = __builtin_fma(-a.cy, dhy, fn);
+            double* dst = base + (int64_t)m * a.nx;
+            if (!BND || (gx < a.nx && y0 + m < a.ny)) {
+                if (NT)
+                    __builtin_nontemporal_store(fn, &dst[(unsigned)lane]);
+                else
+                    dst[(unsigned)lane] = fn;
+            }
+        };
+        if (vy > 0.0) {
+            y_pass<R, false>(s_pl, lane, vy, eps, upd);
+        } else if (vy < 0.0) {
+            y_pass<R, true>(s_pl, lane, vy, eps, upd);
+        } else {
+#pragma unroll
+            for (int m = 0; m < R; ++m) upd(m, s_pl[(m + HALO) * PITCH + lane + HALO], 0.0);
         }
-        stage_store<R, BND>(a, inext, y0, lane, t, s_pl, pre);
-        __syncthreads();
+    };
+
+    double pa[Stage<R>::NPRE], pb[Stage<R>::NPRE];
+    stage_load<R, BND>(a, i0, x0, y0, lane, t, plane, pa);
+    stage_store<R, BND>(a, i0, y0, lane, t, s_pl, pa);
+    __syncthreads();
+    if (DEPTH == 2) stage_load<R, BND>(a, i0 + 1 < iend ? i0 + 1 : i0, x0, y0, lane, t, plane, pb);
+#pragma unroll 1
+    for (int i = i0; i < iend; i += DEPTH) {
+        if (DEPTH == 1) {
+            stage_load<R, BND>(a, i + 1 < iend ? i + 1 : i, x0, y0, lane, t, plane, pa);
+            compute(i);
+            stage_store<R, BND>(a, i + 1 < iend ? i + 1 : i, y0, lane, t, s_pl, pa);
+            __syncthreads();
+        } else {
+            stage_load<R, BND>(a, i + 2 < iend ? i + 2 : i, x0, y0, lane, t, plane, pa);
+            compute(i);
+            stage_store<R, BND>(a, i + 1, y0, lane, t, s_pl, pb);
+            __syncthreads();
+            stage_load<R, BND>(a, i + 3 < iend ? i + 3 : i, x0, y0, lane, t, plane, pb);
+            compute(i + 1);
+            stage_store<R, BND>(a, i + 2 < iend ? i + 2 : i, y0, lane, t, s_pl, pa);
+            __syncthreads();
+        }
     }
 }
 
-template <int R, int G, int W>
+template <int R, int G, int W, int DEPTH, bool NT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_step(StepArgs a)
 {
     __shared__ double s_pl[Stage<R>::SLOTS];
@@ -370,12 +384,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_
         const bool act = gx < a.nx && gy < a.ny;
         double r = 1.0, jx = 0.0, jy = 0.0, E = 1.0, fz = 0.0;
         if (act) {
-            const double* p = a.fin + (int64_t)gy * a.nx + gx;
+            const double* p = a.fin + (int64_t)gy * a.nx + x0;
             r = 0.0;
             E = 0.0;
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
-                const double fi = p[i * plane];
+                const double fi = (p + i * plane)[(unsigned)lane];
                 if (i == 0) fz = fi;
                 r += fi;
                 jx = __builtin_fma(fi, a.k.vx[i], jx);
@@ -398,7 +412,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_
             const double F0 = 1.0 - 6.0 * (weight_c(a.k, 0, c.T) + weight_c(a.k, 1, c.T) +
                                             weight_c(a.k, 2, c.T));
             const double fe = c.rho * F0 * c.t0;
-            a.fout[(int64_t)gy * a.nx + gx] = __builtin_fma(-a.ct, fz - fe, fz);
+            (a.fout + (int64_t)gy * a.nx + x0)[(unsigned)lane] = __builtin_fma(-a.ct, fz - fe, fz);
         }
     }
     if (a.ke_part && grp == 0) {
@@ -413,9 +427,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_
     // ---- phase 2 ----
     const TileMap t = tile_map<R>(a, x0, y0, lane, !interior);
     if (interior)
-        plane_loop<R, G, false>(a, grp, x0, y0, lane, t, plane, s_pl, s_dx, rho, Tm, uxt, uyt, t0);
+        plane_loop<R, G, false, DEPTH, NT>(a, grp, x0, y0, lane, t, plane, s_pl, s_dx, rho, Tm, uxt,
+                                           uyt, t0);
     else
-        plane_loop<R, G, true>(a, grp, x0, y0, lane, t, plane, s_pl, s_dx, rho, Tm, uxt, uyt, t0);
+        plane_loop<R, G, true, DEPTH, NT>(a, grp, x0, y0, lane, t, plane, s_pl, s_dx, rho, Tm, uxt,
+                                          uyt, t0);
 }
 
 // ---------------------------------------------------------------------------
@@ -549,25 +565,32 @@ __global__ __launch_bounds__(256) void k_reduce_pairs(const double* __restrict__
 // Step kernel variants: rows per lane R, velocity groups G, and the
 // wavefronts-per-SIMD target W that bounds the register budget.
 struct StepVariant {
-    int R, G, W;
+    int R, G, W, D, NT;
     void (*kernel)(StepArgs);
 };
 
+// (rows per lane, velocity groups, waves-per-SIMD target, planes in flight,
+// non-temporal stores)
+#define LBM_STEP_VARIANT(R, G, W, D, NT) {R, G, W, D, NT, k_step<R, G, W, D, NT>}
 static const StepVariant kStepVariants[] = {
-    {8, 1, 2, k_step<8, 1, 2>}, {8, 3, 2, k_step<8, 3, 2>}, {4, 1, 3, k_step<4, 1, 3>},
-    {4, 3, 3, k_step<4, 3, 3>}, {4, 2, 3, k_step<4, 2, 3>}, {8, 1, 3, k_step<8, 1, 3>},
-    {2, 3, 4, k_step<2, 3, 4>}, {2, 6, 4, k_step<2, 6, 4>}, {8, 2, 2, k_step<8, 2, 2>},
-    {4, 6, 3, k_step<4, 6, 3>},
+    LBM_STEP_VARIANT(4, 1, 3, 1, 0), LBM_STEP_VARIANT(4, 3, 3, 1, 0), LBM_STEP_VARIANT(8, 2, 2, 1, 0),
+    LBM_STEP_VARIANT(8, 1, 2, 1, 0), LBM_STEP_VARIANT(2, 3, 4, 1, 0), LBM_STEP_VARIANT(4, 1, 3, 2, 0),
+    LBM_STEP_VARIANT(4, 3, 3, 2, 0), LBM_STEP_VARIANT(2, 3, 4, 2, 0), LBM_STEP_VARIANT(2, 1, 4, 2, 0),
+    LBM_STEP_VARIANT(8, 1, 2, 2, 0), LBM_STEP_VARIANT(8, 2, 2, 1, 1), LBM_STEP_VARIANT(4, 1, 3, 2, 1),
+    LBM_STEP_VARIANT(8, 1, 3, 1, 0), LBM_STEP_VARIANT(4, 1, 4, 2, 1), LBM_STEP_VARIANT(4, 3, 4, 1, 0),
 };
+#undef LBM_STEP_VARIANT
 constexpr int kNumStepVariants = sizeof(kStepVariants) / sizeof(kStepVariants[0]);
 
 int step_variant_count() { return kNumStepVariants; }
-int step_variant_desc(int v, int* R, int* G, int* W)
+int step_variant_desc(int v, int* R, int* G, int* W, int* D, int* NT)
 {
     if (v < 0 || v >= kNumStepVariants) return -1;
     *R = kStepVariants[v].R;
     *G = kStepVariants[v].G;
     *W = kStepVariants[v].W;
+    *D = kStepVariants[v].D;
+    *NT = kStepVariants[v].NT;
     return 0;
 }
 

@@ -24,7 +24,7 @@ int lbmi_default_variant(int nx, int ny);
 
 namespace lbmd {
 int step_variant_count();
-int step_variant_desc(int v, int* R, int* G, int* W);
+int step_variant_desc(int v, int* R, int* G, int* W, int* D, int* NT);
 int step_ntiles(int variant, int nx, int ny);
 hipError_t launch_step(int variant, const double* fin, double* fout, const Consts& k,
                        double* ke_part, int nx, int ny, const int bc[4], double cx, double cy,

@@ -87,7 +87,7 @@ def lib():
         "lbm_moments": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
         "lbm_kinetic_y": (C.c_int, [_P, _P, _P, _P]),
         "lbm_step_variant_count": (C.c_int, []),
-        "lbm_step_variant_info": (C.c_int, [_I, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)]),
+        "lbm_step_variant_info": (C.c_int, [_I, C.POINTER(_I)]),
         "lbm_set_step_variant": (C.c_int, [_P, _I]),
         "lbm_get_step_variant": (C.c_int, [_P, C.POINTER(_I)]),
         "lbm_last_error": (C.c_char_p, []),
@@ -174,10 +174,11 @@ def lbm_step_variant_count():
 
 
 def lbm_step_variant_info(v):
-    """(rows per lane R, velocity groups G, waves-per-SIMD target W)."""
-    R, G, W = _I(), _I(), _I()
-    _check(lib().lbm_step_variant_info(int(v), C.byref(R), C.byref(G), C.byref(W)))
-    return R.value, G.value, W.value
+    """(rows per lane R, velocity groups G, waves-per-SIMD target W, planes in
+    flight D, non-temporal stores NT)."""
+    info = (_I * 5)()
+    _check(lib().lbm_step_variant_info(int(v), info))
+    return tuple(int(x) for x in info)
 
 
 def lbm_set_step_variant(h, v):
