@@ -109,6 +109,34 @@ int lbm_moments(lbm_ctx* ctx, const double* f, double* rho, double* ux, double* 
  * rho u_y^2 / 2 of f (device double[2]). */
 int lbm_kinetic_y(lbm_ctx* ctx, const double* f, double* out2, lbm_stream stream);
 
+/* Discrete adjoint of one step (reverse mode of lbm_step with nsteps = 1):
+ *   lam_n = (dS/df)^T lam_np1 + w dE_y/df,   S = the step of Eq. (47),
+ * evaluated at f = f_n, with E_y = sum_cells rho u_y^2 / 2 * dx * dy. The
+ * transpose covers the WENO5 fluxes including their nonlinear weights
+ * (Eqs. (48)-(55)), the equilibrium through the moments (Eqs. (10), (28),
+ * (44)-(46)), the BGK term and the ghost layers (periodic images, mirrored
+ * planes of reflecting walls; fixed-equilibrium ghosts are constants).
+ * f_n, lam_np1: 19-plane inputs; lam_n: 19-plane output (must not overlap
+ * them). Deterministic: every output value is written once. */
+int lbm_adjoint_step(lbm_ctx* ctx, const double* f_n, const double* lam_np1, double w,
+                     double* lam_n, lbm_stream stream);
+
+/* Vector-Jacobian product of lbm_init: g_q = sum_i lam0_i d f_i^eq / d q for
+ * q = rho, ux, uy, T per cell (Eq. (28) with Eqs. (44)-(46)). Inputs: the four
+ * scalar fields lbm_init took and a 19-plane lam0; outputs: four scalar
+ * fields that must not overlap the inputs or each other. */
+int lbm_init_vjp(lbm_ctx* ctx, const double* rho, const double* ux, const double* uy,
+                 const double* T, const double* lam0, double* g_rho, double* g_ux,
+                 double* g_uy, double* g_T, lbm_stream stream);
+
+/* Separable projection of a scalar field g (ny x nx): out[m] =
+ * sum_{y,x} A[m*nx + x] * B[y] * g[y*nx + x] for m < M, in a fixed summation
+ * order (column sums weighted by B, then one dot product per m). Chains the
+ * initial-field gradient to parameters whose tangents factor as
+ * (x profile) x (y profile). A: M x nx, B: ny, out: M (device). */
+int lbm_sep_project(lbm_ctx* ctx, const double* g, const double* A, int32_t M, const double* B,
+                    double* out, lbm_stream stream);
+
 /* Step-kernel variants for the autotuner. lbm_step_variant_info fills
  * info5[0..4] = (R, G, W, D, NT): one-wavefront workgroups own tiles of
  * 64 x R cells and one of G groups of the 18 moving velocities; W is the

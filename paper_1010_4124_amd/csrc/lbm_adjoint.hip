@@ -1,0 +1,476 @@
+// lbm_adjoint.hip -- discrete adjoint of one forward-Euler step of the D2V19
+// FDLB model (arXiv:1010.4124, Eq. (47)) and of the equilibrium
+// initialisation, for gfx950.
+//
+// For the step S(f) with S_i(c) = f_i - cx dh^x_i - cy dh^y_i
+// - ct (f_i - f_i^eq(m(c))), the kernel computes
+//   lambda^n = (dS/df^n)^T lambda^{n+1} + w dE_y/df^n,
+// E_y = sum_c rho u_y^2 / 2 dx dy, in gather form (every output is written
+// once, so the result is deterministic):
+//   lambda_i(c) = (1 - ct) lambda'_i(c)                          (identity, BGK)
+//               + K0 + Kx v_ix + Ky v_iy + KE |v_i|^2/2           (through f^eq and
+//                                                                   the objective)
+//               + v_ix sum_faces mu_x dh/dF + v_iy sum_faces mu_y dh/dF  (WENO)
+// where the per-cell K's hold ct sum_j lambda'_j d f_j^eq / d(rho, j, E) and
+// the objective gradient, and mu of the face between cells I and I+1 is
+// c (lambda'(I+1) - lambda'(I)).
+//
+// A one-wavefront workgroup owns a 64 x R tile. Phase 1 forms the K's of its
+// cells (19 values of f and of lambda' per cell) and writes the rest plane.
+// Phase 2 stages, per moving velocity, f_i with a 4-cell halo and lambda'_i
+// with a 3-cell halo in LDS (lambda' is zero in ghost cells except on
+// periodic axes: ghosts have no update). Each lane recomputes the R+4 faces
+// whose stencils touch its R-cell strip and applies the reverse of the WENO
+// face (weno_face_bar); x strips hand their sums to the column owners through
+// LDS. On a reflecting wall, the ghost values of velocity i are interior
+// values of its mirror j, so cells within three cells of the wall also gather
+// the wall faces of plane j.
+#include "lbm_device.h"
+#include "lbm_internal.h"
+#include "lbm_stage.h"
+
+namespace lbmd {
+
+constexpr int ATX = 64;
+constexpr int AP = 73;      // LDS pitch of the staged f (halo 4) and lambda (halo 3) images
+constexpr int AXP = 65;     // LDS pitch of the x contributions
+constexpr int FH = 4, LH = 3;
+
+struct AdjArgs {
+    const double* __restrict__ f;
+    const double* __restrict__ lam1;
+    double* __restrict__ lam0;
+    int nx, ny;
+    int bc[4];
+    int tiles_x, ntiles, per_xcd;
+    double cx, cy, ct, wdxdy;  // w dx dy: weight of the objective term
+    Consts k;
+};
+
+__device__ __forceinline__ GridBC grid_of(const AdjArgs& a)
+{
+    return GridBC{a.nx, a.ny, {a.bc[0], a.bc[1], a.bc[2], a.bc[3]}};
+}
+
+__device__ __forceinline__ double dweight_c(const Consts& k, int s, double T)
+{
+    // dF_k/dT of T (Fc + T (Fb + T Fa))
+    return __builtin_fma(T, __builtin_fma(3.0 * T, k.Fa[s], 2.0 * k.Fb[s]), k.Fc[s]);
+}
+
+// Gather of one line strip: fw[0..R+7] are f at strip positions -4..R+3,
+// lw[0..R+5] are lambda' at positions -3..R+2; returns in acc[m] the sum over
+// the faces touching strip cell m of mu dh/df(m) (including the factor v).
+template <int R, bool NEG>
+__device__ __forceinline__ void gather_strip(const double (&fw)[R + 8], const double (&lw)[R + 6],
+                                             double v, double cn, double eps, double (&acc)[R])
+{
+    double Pw[R + 8];
+#pragma unroll
+    for (int q = 0; q < R + 8; ++q) Pw[q] = v * (NEG ? fw[R + 7 - q] : fw[q]);
+#pragma unroll
+    for (int m = 0; m < R; ++m) acc[m] = 0.0;
+#pragma unroll
+    for (int t = 0; t < R + 4; ++t) {
+        // face between strip positions I and I+1: I = t-2 (v >= 0) or R-t (v < 0)
+        const double mu = NEG ? cn * (lw[R + 4 - t] - lw[R + 3 - t]) : cn * (lw[t + 2] - lw[t + 1]);
+        double G[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        weno_face_bar(&Pw[t], eps, mu, G);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const int m = NEG ? R + 3 - t - q : t + q - 4;
+            if (m >= 0 && m < R) acc[m] += G[q];
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < R; ++m) acc[m] *= v;
+}
+
+// Value of plane i at (gx, gy) with the forward ghost rules (domain or the
+// three-cell ghost layer of one side; anything else reads as 0).
+__device__ __forceinline__ double f_at(const AdjArgs& a, int i, int gx, int gy)
+{
+    const int64_t plane = (int64_t)a.nx * a.ny;
+    const bool inx = (unsigned)gx < (unsigned)a.nx, iny = (unsigned)gy < (unsigned)a.ny;
+    if (inx && iny) return a.f[i * plane + (int64_t)gy * a.nx + gx];
+    if (inx == iny) return 0.0;
+    const bool xg = !inx;
+    const int n = xg ? a.nx : a.ny, g = xg ? gx : gy;
+    const bool lo = g < 0;
+    const int m = lo ? -1 - g : g - n;
+    if (m >= HALO) return 0.0;
+    const int side = xg ? (lo ? XLO : XHI) : (lo ? YLO : YHI);
+    const int bc = a.bc[side];
+    if (bc == FIXED_EQ) return a.k.side_eq[side][i];
+    int src_i = i, s = wrap_index(g, n);
+    if (bc == REFLECT) {
+        src_i = xg ? a.k.mirx[i] : a.k.miry[i];
+        s = lo ? m : n - 1 - m;
+    }
+    const int sx = xg ? s : gx, sy = xg ? gy : s;
+    return a.f[src_i * plane + (int64_t)sy * a.nx + sx];
+}
+
+__device__ __forceinline__ double lam_at(const AdjArgs& a, int i, int gx, int gy)
+{
+    const int64_t plane = (int64_t)a.nx * a.ny;
+    if ((unsigned)gx < (unsigned)a.nx && (unsigned)gy < (unsigned)a.ny)
+        return a.lam1[i * plane + (int64_t)gy * a.nx + gx];
+    return 0.0;  // only used at positions inside the domain
+}
+
+// Contribution of the wall faces of plane j (mirror of plane i across a
+// reflecting wall) to plane i at wall-local position p in 0..2. Wall-local
+// coordinates run from the wall into the domain; (dx, dy) is that direction,
+// (wx, wy) the global cell at p = 0, vn the velocity component of plane j
+// along it and cn = dt / spacing.
+__device__ __forceinline__ double wall_term(const AdjArgs& a, int j, int wx, int wy, int dx, int dy,
+                                            int p, double vn, double cn)
+{
+    if (vn == 0.0) return 0.0;
+    const double eps = a.k.eps;
+    // F(q) of plane j at wall-local q = -3..4 (q < 0: ghosts = mirror values)
+    double F[8];
+#pragma unroll
+    for (int q = -3; q <= 4; ++q) F[q + 3] = vn * f_at(a, j, wx + q * dx, wy + q * dy);
+    double L[4];  // lambda'_j at q = -1..2 (ghost: zero)
+    L[0] = 0.0;
+#pragma unroll
+    for (int q = 0; q <= 2; ++q) L[q + 1] = lam_at(a, j, wx + q * dx, wy + q * dy);
+    double sum = 0.0;
+    const int ghost = -1 - p;  // the ghost position that holds cell p
+    if (vn > 0.0) {
+#pragma unroll
+        for (int J = -1; J <= 1; ++J) {
+            const double mu = cn * (L[J + 2] - L[J + 1]);
+            double G[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            weno_face_bar(&F[J - 2 + 3], eps, mu, G);  // stencil J-2..J+2
+#pragma unroll
+            for (int q = 0; q < 5; ++q)
+                if (J - 2 + q == ghost) sum += G[q];
+        }
+    } else {
+#pragma unroll
+        for (int J = -1; J <= 0; ++J) {
+            const double mu = cn * (L[J + 2] - L[J + 1]);
+            double P[5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) P[q] = F[J + 3 - q + 3];  // stencil J+3..J-1
+            double G[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            weno_face_bar(P, eps, mu, G);
+#pragma unroll
+            for (int q = 0; q < 5; ++q)
+                if (J + 3 - q == ghost) sum += G[q];
+        }
+    }
+    return vn * sum;
+}
+
+template <int R, bool BND>
+__device__ __forceinline__ void adj_planes(const AdjArgs& a, int x0, int y0, int lane,
+                                           const TileMapG& tf, const TileMapG& tl, double* s_f,
+                                           double* s_l, double* s_ax, const double (&K0)[R],
+                                           const double (&Kx)[R], const double (&Ky)[R],
+                                           const double (&KE)[R])
+{
+    using SF = StageG<R, FH, AP>;
+    using SL = StageG<R, LH, AP>;
+    const GridBC g = grid_of(a);
+    const int64_t plane = (int64_t)a.nx * a.ny;
+    const int gx = x0 + lane;
+    const double omct = 1.0 - a.ct, eps = a.k.eps;
+    const bool wall_ylo = a.bc[YLO] == REFLECT && y0 < HALO;
+    const bool wall_yhi = a.bc[YHI] == REFLECT && y0 + R > a.ny - HALO;
+    const bool wall_xlo = a.bc[XLO] == REFLECT && x0 < HALO;
+    const bool wall_xhi = a.bc[XHI] == REFLECT && x0 + ATX > a.nx - HALO;
+#pragma unroll 1
+    for (int i = 1; i < NV; ++i) {
+        double pf[SF::NPRE], pl[SL::NPRE];
+        stage_load_g<R, FH, AP, BND, false>(a.f, g, a.k, i, x0, y0, lane, tf, plane, pf);
+        stage_load_g<R, LH, AP, BND, true>(a.lam1, g, a.k, i, x0, y0, lane, tl, plane, pl);
+        stage_store_g<R, FH, AP, BND, false>(g, a.k, i, y0, lane, tf, s_f, pf);
+        stage_store_g<R, LH, AP, BND, true>(g, a.k, i, y0, lane, tl, s_l, pl);
+        __syncthreads();
+        const double vx = a.k.vx[i], vy = a.k.vy[i];
+        {  // x strips: lane -> (row r = lane % R, strip s = lane / R)
+            const int r = lane % R, s = lane / R;
+            double fw[R + 8], lw[R + 6], acc[R];
+#pragma unroll
+            for (int q = 0; q < R + 8; ++q) fw[q] = s_f[(r + FH) * AP + s * R + q];
+#pragma unroll
+            for (int q = 0; q < R + 6; ++q) lw[q] = s_l[(r + LH) * AP + s * R + q];
+            if (vx < 0.0)
+                gather_strip<R, true>(fw, lw, vx, a.cx, eps, acc);
+            else
+                gather_strip<R, false>(fw, lw, vx, a.cx, eps, acc);
+#pragma unroll
+            for (int m = 0; m < R; ++m) s_ax[r * AXP + s * R + m] = acc[m];
+        }
+        __syncthreads();
+        double accy[R];
+        if (vy != 0.0) {
+            double fw[R + 8], lw[R + 6];
+#pragma unroll
+            for (int q = 0; q < R + 8; ++q) fw[q] = s_f[q * AP + lane + FH];
+#pragma unroll
+            for (int q = 0; q < R + 6; ++q) lw[q] = s_l[q * AP + lane + LH];
+            if (vy < 0.0)
+                gather_strip<R, true>(fw, lw, vy, a.cy, eps, accy);
+            else
+                gather_strip<R, false>(fw, lw, vy, a.cy, eps, accy);
+        } else {
+#pragma unroll
+            for (int m = 0; m < R; ++m) accy[m] = 0.0;
+        }
+        double* dst = a.lam0 + i * plane + (int64_t)y0 * a.nx + x0;
+        const double hv2 = a.k.hv2[i];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int gy = y0 + m;
+            const double lc = s_l[(m + LH) * AP + lane + LH];
+            double out = __builtin_fma(omct, lc, K0[m]);
+            out = __builtin_fma(Kx[m], vx, out);
+            out = __builtin_fma(Ky[m], vy, out);
+            out = __builtin_fma(KE[m], hv2, out);
+            out += s_ax[m * AXP + lane] + accy[m];
+            if (BND) {
+                // reflecting walls: gather the wall faces of the mirrored plane
+                if (wall_ylo && gy < HALO)
+                    out += wall_term(a, a.k.miry[i], gx, 0, 0, 1, gy, a.k.vy[a.k.miry[i]], a.cy);
+                if (wall_yhi && gy >= a.ny - HALO && gy < a.ny)
+                    out += wall_term(a, a.k.miry[i], gx, a.ny - 1, 0, -1, a.ny - 1 - gy,
+                                     -a.k.vy[a.k.miry[i]], a.cy);
+                if (wall_xlo && gx < HALO)
+                    out += wall_term(a, a.k.mirx[i], 0, gy, 1, 0, gx, a.k.vx[a.k.mirx[i]], a.cx);
+                if (wall_xhi && gx >= a.nx - HALO && gx < a.nx)
+                    out += wall_term(a, a.k.mirx[i], a.nx - 1, gy, -1, 0, a.nx - 1 - gx,
+                                     -a.k.vx[a.k.mirx[i]], a.cx);
+            }
+            if (!BND || (gx < a.nx && gy < a.ny)) dst[(int64_t)m * a.nx + (unsigned)lane] = out;
+        }
+        __syncthreads();
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(64) void k_adjoint(AdjArgs a)
+{
+    using SF = StageG<R, FH, AP>;
+    using SL = StageG<R, LH, AP>;
+    __shared__ double s_f[SF::SLOTS];
+    __shared__ double s_l[SL::SLOTS];
+    __shared__ double s_ax[R * AXP];
+
+    const int b = blockIdx.x;
+    const int tile = (b & 7) * a.per_xcd + (b >> 3);
+    if (tile >= a.ntiles) return;
+    const int lane = threadIdx.x;
+    const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
+    const int x0 = tx * ATX, y0 = ty * R;
+    const int64_t plane = (int64_t)a.nx * a.ny;
+    const int gx = x0 + lane;
+    const bool interior =
+        x0 >= FH && x0 + ATX + FH <= a.nx && y0 >= FH && y0 + R + FH <= a.ny;
+
+    // ---- phase 1: per-cell adjoint of the equilibrium and the objective ----
+    double K0[R], Kx[R], Ky[R], KE[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const int gy = y0 + m;
+        const bool act = gx < a.nx && gy < a.ny;
+        K0[m] = Kx[m] = Ky[m] = KE[m] = 0.0;
+        if (!act) continue;
+        const double* pf = a.f + (int64_t)gy * a.nx + x0;
+        const double* pl = a.lam1 + (int64_t)gy * a.nx + x0;
+        double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const double fi = (pf + i * plane)[(unsigned)lane];
+            r += fi;
+            jx = __builtin_fma(fi, a.k.vx[i], jx);
+            jy = __builtin_fma(fi, a.k.vy[i], jy);
+            E = __builtin_fma(fi, a.k.hv2[i], E);
+        }
+        const double ux = jx / r, uy = jy / r;
+        const double u2 = ux * ux + uy * uy;
+        const double T = E / r - 0.5 * u2;
+        const double iT = 1.0 / T;
+        const double t0 = 1.0 - u2 / (2.0 * T);
+        const double b = 1.0 - t0;
+        double Fk[4], dF[4];
+        Fk[1] = weight_c(a.k, 0, T);
+        Fk[2] = weight_c(a.k, 1, T);
+        Fk[3] = weight_c(a.k, 2, T);
+        Fk[0] = 1.0 - 6.0 * (Fk[1] + Fk[2] + Fk[3]);
+        dF[1] = dweight_c(a.k, 0, T);
+        dF[2] = dweight_c(a.k, 1, T);
+        dF[3] = dweight_c(a.k, 2, T);
+        dF[0] = -6.0 * (dF[1] + dF[2] + dF[3]);
+        // sums over i of lambda'_i times the partials of f_i^eq (Eq. (28)),
+        // with P = (1-b)(1+eta) + eta^2/2 + eta^3/6, eta = v.u / T
+        double sP = 0.0, sX = 0.0, sY = 0.0, sT = 0.0, l0 = 0.0;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const double L = (pl + i * plane)[(unsigned)lane];
+            if (i == 0) l0 = L;
+            const int s = i == 0 ? 0 : 1 + (i - 1) / 6;
+            const double eta = __builtin_fma(a.k.vx[i], ux * iT, a.k.vy[i] * (uy * iT));
+            const double P = feq_poly(eta, t0);
+            const double Pxi = t0 + eta * (1.0 + 0.5 * eta);        // T dP/dxi
+            const double Pb = -(1.0 + eta);                          // dP/db
+            const double PTT = -eta * (t0 + eta * (1.0 + 0.5 * eta));  // T dP/dT at fixed xi, b
+            const double LF = L * Fk[s];
+            sP = __builtin_fma(LF, P, sP);
+            sX = __builtin_fma(LF, __builtin_fma(Pxi, a.k.vx[i], Pb * ux), sX);
+            sY = __builtin_fma(LF, __builtin_fma(Pxi, a.k.vy[i], Pb * uy), sY);
+            sT += L * __builtin_fma(dF[s] * T, P, Fk[s] * (PTT - Pb * b));
+        }
+        // f^eq depends on (rho, ux, uy, T): d/drho = F P, d/du = rho F (Pxi v + Pb u)/T,
+        // d/dT = rho (F' P + F (PTT - Pb b) / T)
+        double rb = sP, uxb = r * iT * sX, uyb = r * iT * sY, Tb = r * iT * sT;
+        // T = E/rho - u^2/2, u = j/rho
+        const double Eb = Tb / r;
+        rb -= Tb * (E / (r * r));
+        const double uxb2 = uxb - Tb * ux, uyb2 = uyb - Tb * uy;
+        const double jxb = uxb2 / r, jyb = uyb2 / r;
+        rb -= (uxb2 * ux + uyb2 * uy) / r;
+        K0[m] = __builtin_fma(a.ct, rb, -0.5 * a.wdxdy * uy * uy);
+        Kx[m] = a.ct * jxb;
+        Ky[m] = __builtin_fma(a.ct, jyb, a.wdxdy * uy);
+        KE[m] = a.ct * Eb;
+        // rest particle: no convection
+        (a.lam0 + (int64_t)gy * a.nx + x0)[(unsigned)lane] = __builtin_fma(1.0 - a.ct, l0, K0[m]);
+    }
+
+    // ---- phase 2: the 18 moving velocities ----
+    const GridBC g = grid_of(a);
+    const TileMapG tf = tile_map_g<R, FH, false>(g, x0, y0, lane, !interior);
+    const TileMapG tl = tile_map_g<R, LH, true>(g, x0, y0, lane, !interior);
+    if (interior)
+        adj_planes<R, false>(a, x0, y0, lane, tf, tl, s_f, s_l, s_ax, K0, Kx, Ky, KE);
+    else
+        adj_planes<R, true>(a, x0, y0, lane, tf, tl, s_f, s_l, s_ax, K0, Kx, Ky, KE);
+}
+
+// ---------------------------------------------------------------------------
+// VJP of the equilibrium initialisation: g_q = sum_i lam_i d f_i^eq / d q for
+// q in (rho, ux, uy, T), one thread per cell.
+__global__ void k_init_vjp(const double* __restrict__ rho, const double* __restrict__ ux,
+                           const double* __restrict__ uy, const double* __restrict__ T,
+                           const double* __restrict__ lam, double* __restrict__ grho,
+                           double* __restrict__ gux, double* __restrict__ guy,
+                           double* __restrict__ gT, int64_t n, Consts k)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const double r = rho[c], u = ux[c], v = uy[c], t = T[c];
+    const double iT = 1.0 / t;
+    const double t0 = 1.0 - (u * u + v * v) / (2.0 * t);
+    const double b = 1.0 - t0;
+    double Fk[4], dF[4];
+    Fk[1] = weight_c(k, 0, t);
+    Fk[2] = weight_c(k, 1, t);
+    Fk[3] = weight_c(k, 2, t);
+    Fk[0] = 1.0 - 6.0 * (Fk[1] + Fk[2] + Fk[3]);
+    dF[1] = dweight_c(k, 0, t);
+    dF[2] = dweight_c(k, 1, t);
+    dF[3] = dweight_c(k, 2, t);
+    dF[0] = -6.0 * (dF[1] + dF[2] + dF[3]);
+    double sP = 0.0, sX = 0.0, sY = 0.0, sT = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const double L = lam[i * n + c];
+        const int s = i == 0 ? 0 : 1 + (i - 1) / 6;
+        const double eta = __builtin_fma(k.vx[i], u * iT, k.vy[i] * (v * iT));
+        const double P = feq_poly(eta, t0);
+        const double Pxi = t0 + eta * (1.0 + 0.5 * eta);
+        const double Pb = -(1.0 + eta);
+        const double PTT = -eta * (t0 + eta * (1.0 + 0.5 * eta));
+        const double LF = L * Fk[s];
+        sP = __builtin_fma(LF, P, sP);
+        sX = __builtin_fma(LF, __builtin_fma(Pxi, k.vx[i], Pb * u), sX);
+        sY = __builtin_fma(LF, __builtin_fma(Pxi, k.vy[i], Pb * v), sY);
+        sT += L * __builtin_fma(dF[s] * t, P, Fk[s] * (PTT - Pb * b));
+    }
+    grho[c] = sP;
+    gux[c] = r * iT * sX;
+    guy[c] = r * iT * sY;
+    gT[c] = r * iT * sT;
+}
+
+// out[m] = sum_{y,x} A[m, x] B[y] g[y, x] in two deterministic passes: column
+// sums weighted by B, then the row products with A.
+__global__ __launch_bounds__(256) void k_colsum(const double* __restrict__ g,
+                                                const double* __restrict__ B, int nx, int ny,
+                                                double* __restrict__ col)
+{
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= nx) return;
+    double s = 0.0;
+    for (int y = 0; y < ny; ++y) s = __builtin_fma(B[y], g[(int64_t)y * nx + x], s);
+    col[x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_rowdot(const double* __restrict__ A,
+                                                const double* __restrict__ col, int nx, int M,
+                                                double* __restrict__ out)
+{
+    __shared__ double sr[4];
+    const int m = blockIdx.x;
+    if (m >= M) return;
+    double s = 0.0;
+    for (int x = threadIdx.x; x < nx; x += 256) s = __builtin_fma(A[(int64_t)m * nx + x], col[x], s);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) sr[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[m] = sr[0] + sr[1] + sr[2] + sr[3];
+}
+
+// ---------------------------------------------------------------------------
+constexpr int ADJ_R = 4;
+
+hipError_t launch_adjoint(const double* f, const double* lam1, double* lam0, const Consts& k,
+                          int nx, int ny, const int bc[4], double cx, double cy, double ct,
+                          double wdxdy, hipStream_t st)
+{
+    AdjArgs a;
+    a.f = f;
+    a.lam1 = lam1;
+    a.lam0 = lam0;
+    a.nx = nx;
+    a.ny = ny;
+    for (int s = 0; s < 4; ++s) a.bc[s] = bc[s];
+    a.tiles_x = (nx + ATX - 1) / ATX;
+    a.ntiles = a.tiles_x * ((ny + ADJ_R - 1) / ADJ_R);
+    a.per_xcd = (a.ntiles + 7) / 8;
+    a.cx = cx;
+    a.cy = cy;
+    a.ct = ct;
+    a.wdxdy = wdxdy;
+    a.k = k;
+    hipLaunchKernelGGL(k_adjoint<ADJ_R>, dim3(8 * a.per_xcd), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_vjp(const double* rho, const double* ux, const double* uy, const double* T,
+                           const double* lam, double* grho, double* gux, double* guy, double* gT,
+                           const Consts& k, int64_t n, hipStream_t st)
+{
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_init_vjp, dim3((unsigned)blocks), dim3(256), 0, st, rho, ux, uy, T, lam,
+                       grho, gux, guy, gT, n, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_sep_project(const double* g, const double* A, const double* B, int nx, int ny,
+                              int M, double* col, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_colsum, dim3((nx + 255) / 256), dim3(256), 0, st, g, B, nx, ny, col);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rowdot, dim3(M), dim3(256), 0, st, A, col, nx, M, out);
+    return hipGetLastError();
+}
+
+}  // namespace lbmd

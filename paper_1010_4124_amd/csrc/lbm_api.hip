@@ -119,7 +119,8 @@ int lbm_create(const lbm_params* p, lbm_ctx** out)
     // the same buffer first receives the 4 x 19 fixed-side equilibria
     if (2 * c->ke_cap < 4 * NV) c->ke_cap = 2 * NV;
     if ((e = hipMalloc(&c->scratch, NV * n * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&c->ke_part, 2 * (size_t)c->ke_cap * sizeof(double))) != hipSuccess) {
+        (e = hipMalloc(&c->ke_part, 2 * (size_t)c->ke_cap * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&c->colbuf, (size_t)p->nx * sizeof(double))) != hipSuccess) {
         lbm_destroy(c);
         g_err = std::string("hipMalloc: ") + hipGetErrorString(e);
         return LBM_ENOMEM;
@@ -143,6 +144,7 @@ void lbm_destroy(lbm_ctx* c)
     hipDeviceSynchronize();
     if (c->scratch) hipFree(c->scratch);
     if (c->ke_part) hipFree(c->ke_part);
+    if (c->colbuf) hipFree(c->colbuf);
     delete c;
 }
 
@@ -266,4 +268,49 @@ int lbmi_default_variant(int nx, int ny)
             return v;
     }
     return 0;
+}
+
+int lbm_adjoint_step(lbm_ctx* c, const double* f_n, const double* lam_np1, double w, double* lam_n,
+                     lbm_stream stream)
+{
+    if (!c || !f_n || !lam_np1 || !lam_n) return fail(LBM_EINVAL, "null argument%s%lld");
+    const lbm_params& p = c->p;
+    const size_t fb = NV * (size_t)p.nx * p.ny * sizeof(double);
+    if (overlaps(lam_n, fb, lam_np1, fb) || overlaps(lam_n, fb, f_n, fb))
+        return fail(LBM_EINVAL, "lam_n overlaps an input%s%lld");
+    hipError_t e = launch_adjoint(f_n, lam_np1, lam_n, c->k, p.nx, p.ny, p.bc, p.dt / p.dx,
+                                  p.dt / p.dy, p.dt / p.tau, w * p.dx * p.dy, (hipStream_t)stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_adjoint_step");
+}
+
+int lbm_init_vjp(lbm_ctx* c, const double* rho, const double* ux, const double* uy, const double* T,
+                 const double* lam0, double* g_rho, double* g_ux, double* g_uy, double* g_T,
+                 lbm_stream stream)
+{
+    if (!c || !rho || !ux || !uy || !T || !lam0 || !g_rho || !g_ux || !g_uy || !g_T)
+        return fail(LBM_EINVAL, "null argument%s%lld");
+    const int64_t n = (int64_t)c->p.nx * c->p.ny;
+    const size_t sb = n * sizeof(double), fb = NV * sb;
+    const double* ins[5] = {rho, ux, uy, T, lam0};
+    const size_t insz[5] = {sb, sb, sb, sb, fb};
+    double* outs[4] = {g_rho, g_ux, g_uy, g_T};
+    for (int o = 0; o < 4; ++o) {
+        for (int q = 0; q < 5; ++q)
+            if (overlaps(outs[o], sb, ins[q], insz[q]))
+                return fail(LBM_EINVAL, "an output overlaps an input%s%lld");
+        for (int q = o + 1; q < 4; ++q)
+            if (overlaps(outs[o], sb, outs[q], sb)) return fail(LBM_EINVAL, "outputs overlap%s%lld");
+    }
+    hipError_t e = launch_init_vjp(rho, ux, uy, T, lam0, g_rho, g_ux, g_uy, g_T, c->k, n,
+                                   (hipStream_t)stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_init_vjp");
+}
+
+int lbm_sep_project(lbm_ctx* c, const double* g, const double* A, int32_t M, const double* B,
+                    double* out, lbm_stream stream)
+{
+    if (!c || !g || !A || !B || !out || M < 1) return fail(LBM_EINVAL, "bad argument%s%lld");
+    const lbm_params& p = c->p;
+    hipError_t e = launch_sep_project(g, A, B, p.nx, p.ny, M, c->colbuf, out, (hipStream_t)stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_sep_project");
 }

@@ -180,3 +180,70 @@ __host__ __device__ __forceinline__ int wrap_index(int g, int n)
 }
 
 }  // namespace lbmd
+
+namespace lbmd {
+
+// Reverse mode of one WENO5 face of weno_faces: for the upwind-ordered
+// samples (a, b, c, d, e) = P[0..4] and the adjoint mu of the face flux,
+// adds mu * dh/dP[k] to G[k]. It differentiates the same function (Eqs.
+// (48)-(55)) in the same regrouped variables as the forward code.
+__host__ __device__ __forceinline__ void weno_face_bar(const double* P, double eps, double mu,
+                                                       double* G)
+{
+    constexpr double C13 = 13.0 / 12.0;
+    const double g0 = P[1] - P[0], g1 = P[2] - P[1], g2 = P[3] - P[2], g3 = P[4] - P[3];
+    const double D0 = g1 - g0, D1 = g2 - g1, D2 = g3 - g2;
+    const double E0 = __builtin_fma(C13 * D0, D0, eps);
+    const double E1 = __builtin_fma(C13 * D1, D1, eps);
+    const double E2 = __builtin_fma(C13 * D2, D2, eps);
+    const double b1 = __builtin_fma(0.5, D0, g1);
+    const double b2 = 0.5 * (g1 + g2);
+    const double b3 = __builtin_fma(0.5, D2, -g2);
+    const double Q1 = __builtin_fma(b1, b1, E0);
+    const double Q2 = __builtin_fma(b2, b2, E1);
+    const double Q3 = __builtin_fma(b3, b3, E2);
+    const double q1 = Q1 * Q1, q2 = Q2 * Q2, q3 = Q3 * Q3;
+    const double W1 = q2 * q3, W2 = 6.0 * (q1 * q3), W3 = 3.0 * (q1 * q2);
+    const double r1 = (5.0 / 6.0) * g1 - (1.0 / 3.0) * g0;
+    const double r2 = (1.0 / 6.0) * g1 + (1.0 / 3.0) * g2;
+    const double r3 = (2.0 / 3.0) * g2 - (1.0 / 6.0) * g3;
+    const double iden = 1.0 / (W1 + W2 + W3);
+    const double hq = (W1 * r1 + W2 * r2 + W3 * r3) * iden;  // h - c
+    // h = c + (sum W_q r_q) / (sum W_q)
+    const double r1b = mu * W1 * iden, r2b = mu * W2 * iden, r3b = mu * W3 * iden;
+    const double W1b = mu * (r1 - hq) * iden, W2b = mu * (r2 - hq) * iden,
+                 W3b = mu * (r3 - hq) * iden;
+    // W1 = q2 q3, W2 = 6 q1 q3, W3 = 3 q1 q2
+    const double q1b = 6.0 * W2b * q3 + 3.0 * W3b * q2;
+    const double q2b = W1b * q3 + 3.0 * W3b * q1;
+    const double q3b = W1b * q2 + 6.0 * W2b * q1;
+    // q = Q^2, Q = b^2 + E
+    const double Q1b = 2.0 * Q1 * q1b, Q2b = 2.0 * Q2 * q2b, Q3b = 2.0 * Q3 * q3b;
+    const double b1b = 2.0 * b1 * Q1b, b2b = 2.0 * b2 * Q2b, b3b = 2.0 * b3 * Q3b;
+    // E_k = 13/12 D_k^2 + eps
+    double D0b = 2.0 * C13 * D0 * Q1b, D1b = 2.0 * C13 * D1 * Q2b, D2b = 2.0 * C13 * D2 * Q3b;
+    // b1 = D0/2 + g1, b2 = (g1 + g2)/2, b3 = D2/2 - g2
+    D0b += 0.5 * b1b;
+    D2b += 0.5 * b3b;
+    double g0b = 0.0, g1b = b1b + 0.5 * b2b, g2b = 0.5 * b2b - b3b, g3b = 0.0;
+    // r's
+    g1b += (5.0 / 6.0) * r1b + (1.0 / 6.0) * r2b;
+    g0b -= (1.0 / 3.0) * r1b;
+    g2b += (1.0 / 3.0) * r2b + (2.0 / 3.0) * r3b;
+    g3b -= (1.0 / 6.0) * r3b;
+    // D_k = g_{k+1} - g_k
+    g1b += D0b;
+    g0b -= D0b;
+    g2b += D1b;
+    g1b -= D1b;
+    g3b += D2b;
+    g2b -= D2b;
+    // g_k = P_{k+1} - P_k, and c = P[2]
+    G[0] += -g0b;
+    G[1] += g0b - g1b;
+    G[2] += g1b - g2b + mu;
+    G[3] += g2b - g3b;
+    G[4] += g3b;
+}
+
+}  // namespace lbmd

@@ -31,6 +31,7 @@
 // arguments and are read with scalar loads.
 #include "lbm_device.h"
 #include "lbm_internal.h"
+#include "lbm_stage.h"
 
 namespace lbmd {
 
@@ -49,184 +50,12 @@ struct StepArgs {
     Consts k;
 };
 
-// ---------------------------------------------------------------------------
-// Staging of one plane of a tile into LDS.
-//
-// The staged image has R+6 rows (three halo rows above and below the tile) of
-// PITCH doubles; column lx = -3..66 sits at lx+3. Every row is one 64-lane
-// load (lane = column 0..63) from a wavefront-uniform row base; the six halo
-// columns of the R centre rows come from one more load in which lane l < 6R
-// takes row l/6 and column -3,-2,-1,64,65,66. A plane thus costs R+7 loads
-// per lane.
-//
-// Interior tiles (tile plus halo inside the domain) need nothing else. A tile
-// touching the boundary gets a per-lane column map once (source column and
-// kind of the row-load lane and of the halo lane) and resolves ghost rows with
-// uniform logic: a row outside the domain is a periodic wrap, a mirror row of
-// the y-mirrored velocity (reflecting wall), a constant (fixed equilibrium) or
-// unused. Constants and unused slots are substituted when the staged values
-// are written to LDS, so no load result is consumed before the next plane.
-enum { CK_NORM = 0, CK_MIRX = 1, CK_CXLO = 2, CK_CXHI = 3, CK_NONE = 4 };
-enum { RM_NORM = 0, RM_MIRY = 1, RM_CONST = 2, RM_NONE = 3 };
-
 template <int R>
-struct Stage {
-    static constexpr int ROWS = R + 2 * HALO;
-    static constexpr int NPRE = ROWS + 1;
-    static constexpr int PAD = ROWS * PITCH;  // 64 pad slots for idle halo lanes
-    static constexpr int SLOTS = PAD + 64;
-    static_assert(6 * R <= 64, "the x-halo of the tile must fit one 64-lane load");
-};
+using Stage = StageG<R, HALO, PITCH>;
 
-struct TileMap {
-    int hrow, hlx;     // halo lane: tile row and column (-3..-1, 64..66)
-    int mcol, mkind;   // row-load lane: source column and kind (boundary tiles)
-    int hcol, hkind;   // halo lane: source column and kind (boundary tiles)
-};
-
-// Source column of global column gx for a row inside the domain.
-__device__ __forceinline__ void x_source(const StepArgs& a, int gx, int& col, int& kind)
+__device__ __forceinline__ GridBC grid_of(const StepArgs& a)
 {
-    if (gx >= 0 && gx < a.nx) {
-        col = gx;
-        kind = CK_NORM;
-        return;
-    }
-    const bool lo = gx < 0;
-    const int m = lo ? -1 - gx : gx - a.nx;
-    col = 0;
-    kind = CK_NONE;
-    if (m >= HALO) return;
-    const int bc = lo ? a.bc[XLO] : a.bc[XHI];
-    if (bc == PERIODIC) {
-        col = wrap_index(gx, a.nx);
-        kind = CK_NORM;
-    } else if (bc == REFLECT) {
-        col = lo ? m : a.nx - 1 - m;
-        kind = CK_MIRX;
-    } else {
-        kind = lo ? CK_CXLO : CK_CXHI;
-    }
-}
-
-template <int R>
-__device__ __forceinline__ TileMap tile_map(const StepArgs& a, int x0, int y0, int lane, bool bnd)
-{
-    TileMap t;
-    const bool hl = lane < 6 * R;
-    const int r = lane / 6, c = lane - 6 * (lane / 6);
-    t.hrow = hl ? r : 0;
-    t.hlx = hl ? (c < 3 ? c - 3 : c + 61) : 0;
-    t.mcol = lane;
-    t.mkind = CK_NORM;
-    t.hcol = 0;
-    t.hkind = CK_NONE;
-    if (bnd) {
-        x_source(a, x0 + lane, t.mcol, t.mkind);
-        if (hl && y0 + r < a.ny) x_source(a, x0 + t.hlx, t.hcol, t.hkind);
-    }
-    return t;
-}
-
-// Uniform description of global row gy: mode and source row.
-struct RowDesc {
-    int mode, src, side;
-};
-
-__device__ __forceinline__ RowDesc row_desc(const StepArgs& a, int gy)
-{
-    RowDesc d{RM_NORM, gy, 0};
-    if (gy >= 0 && gy < a.ny) return d;
-    const bool lo = gy < 0;
-    const int m = lo ? -1 - gy : gy - a.ny;
-    d.side = lo ? YLO : YHI;
-    d.src = 0;
-    if (m >= HALO) {
-        d.mode = RM_NONE;
-        return d;
-    }
-    const int bc = lo ? a.bc[YLO] : a.bc[YHI];
-    if (bc == PERIODIC) {
-        d.src = wrap_index(gy, a.ny);
-    } else if (bc == REFLECT) {
-        d.mode = RM_MIRY;
-        d.src = lo ? m : a.ny - 1 - m;
-    } else {
-        d.mode = RM_CONST;
-    }
-    return d;
-}
-
-template <int R, bool BND>
-__device__ __forceinline__ void stage_load(const StepArgs& a, int i, int x0, int y0, int lane,
-                                           const TileMap& t, int64_t plane,
-                                           double (&pre)[Stage<R>::NPRE])
-{
-    if (!BND) {
-        const unsigned ul = (unsigned)lane;
-#pragma unroll
-        for (int r = 0; r < Stage<R>::ROWS; ++r) {
-            const double* row = a.fin + i * plane + (int64_t)(y0 - HALO + r) * a.nx + x0;
-            pre[r] = row[ul];
-        }
-        // halo columns: offset from column x0 - 3 so that it is never negative
-        const double* hb = a.fin + i * plane + (int64_t)y0 * a.nx + x0 - HALO;
-        pre[Stage<R>::ROWS] = hb[(unsigned)(t.hrow * a.nx + t.hlx + HALO)];
-    } else {
-        const int64_t pi = i * plane, px = a.k.mirx[i] * plane, py = a.k.miry[i] * plane;
-#pragma unroll
-        for (int r = 0; r < Stage<R>::ROWS; ++r) {
-            const RowDesc d = row_desc(a, y0 - HALO + r);
-            int64_t off;
-            if (d.mode == RM_NORM)
-                off = (t.mkind == CK_MIRX ? px : pi) + (int64_t)d.src * a.nx + t.mcol;
-            else if (d.mode == RM_MIRY)
-                off = py + (int64_t)d.src * a.nx + t.mcol;
-            else
-                off = 0;
-            pre[r] = a.fin[off];
-        }
-        const int64_t hoff = t.hkind == CK_NONE
-                                 ? 0
-                                 : (t.hkind == CK_MIRX ? px : pi) + (int64_t)(y0 + t.hrow) * a.nx + t.hcol;
-        pre[Stage<R>::ROWS] = a.fin[hoff];
-    }
-}
-
-template <int R, bool BND>
-__device__ __forceinline__ void stage_store(const StepArgs& a, int i, int y0, int lane,
-                                            const TileMap& t, double* s_pl,
-                                            const double (&pre)[Stage<R>::NPRE])
-{
-    if (!BND) {
-#pragma unroll
-        for (int r = 0; r < Stage<R>::ROWS; ++r) s_pl[r * PITCH + lane + HALO] = pre[r];
-    } else {
-        const double cxl = a.k.side_eq[XLO][i], cxh = a.k.side_eq[XHI][i];
-#pragma unroll
-        for (int r = 0; r < Stage<R>::ROWS; ++r) {
-            const RowDesc d = row_desc(a, y0 - HALO + r);
-            double v = pre[r];
-            if (d.mode == RM_CONST)
-                v = a.k.side_eq[d.side][i];
-            else if (d.mode == RM_NONE)
-                v = 0.0;
-            else if (d.mode == RM_NORM)
-                v = t.mkind == CK_CXLO ? cxl
-                    : t.mkind == CK_CXHI ? cxh
-                    : t.mkind == CK_NONE ? 0.0
-                                         : v;
-            s_pl[r * PITCH + lane + HALO] = v;
-        }
-    }
-    double h = pre[Stage<R>::ROWS];
-    if (BND)
-        h = t.hkind == CK_CXLO ? a.k.side_eq[XLO][i]
-            : t.hkind == CK_CXHI ? a.k.side_eq[XHI][i]
-            : t.hkind == CK_NONE ? 0.0
-                                 : h;
-    const int slot = lane < 6 * R ? (t.hrow + HALO) * PITCH + t.hlx + HALO : Stage<R>::PAD + lane;
-    s_pl[slot] = h;
+    return GridBC{a.nx, a.ny, {a.bc[0], a.bc[1], a.bc[2], a.bc[3]}};
 }
 
 // x pass: lane -> (row r = lane % R, strip s = lane / R); the flux
@@ -279,7 +108,7 @@ __device__ __forceinline__ double wave_max(double v)
 // staged plane never waits for stores.
 template <int R, int G, bool BND, int DEPTH, bool NT>
 __device__ __forceinline__ void plane_loop(const StepArgs& a, int grp, int x0, int y0, int lane,
-                                           const TileMap& t, int64_t plane, double* s_pl,
+                                           const TileMapG& t, int64_t plane, double* s_pl,
                                            double* s_dx, const double (&rho)[R],
                                            const double (&Tm)[R], const double (&uxt)[R],
                                            const double (&uyt)[R], const double (&t0)[R])
@@ -291,6 +120,7 @@ __device__ __forceinline__ void plane_loop(const StepArgs& a, int grp, int x0, i
     double A[R];  // (dt/tau) rho F_k(T) of the current speed shell
     int kcur = -1;
     const double omct = 1.0 - a.ct;
+    const GridBC g = grid_of(a);
 
     // f' = f - cx dh^x - cy dh^y - ct (f - f^eq)
     //    = (1 - ct) f + (ct rho F_k) poly(eta) - cx dh^x - cy dh^y
@@ -333,25 +163,25 @@ __device__ __forceinline__ void plane_loop(const StepArgs& a, int grp, int x0, i
     };
 
     double pa[Stage<R>::NPRE], pb[Stage<R>::NPRE];
-    stage_load<R, BND>(a, i0, x0, y0, lane, t, plane, pa);
-    stage_store<R, BND>(a, i0, y0, lane, t, s_pl, pa);
+    stage_load_g<R, HALO, PITCH, BND, false>(a.fin, g, a.k, i0, x0, y0, lane, t, plane, pa);
+    stage_store_g<R, HALO, PITCH, BND, false>(g, a.k, i0, y0, lane, t, s_pl, pa);
     __syncthreads();
-    if (DEPTH == 2) stage_load<R, BND>(a, i0 + 1 < iend ? i0 + 1 : i0, x0, y0, lane, t, plane, pb);
+    if (DEPTH == 2) stage_load_g<R, HALO, PITCH, BND, false>(a.fin, g, a.k, i0 + 1 < iend ? i0 + 1 : i0, x0, y0, lane, t, plane, pb);
 #pragma unroll 1
     for (int i = i0; i < iend; i += DEPTH) {
         if (DEPTH == 1) {
-            stage_load<R, BND>(a, i + 1 < iend ? i + 1 : i, x0, y0, lane, t, plane, pa);
+            stage_load_g<R, HALO, PITCH, BND, false>(a.fin, g, a.k, i + 1 < iend ? i + 1 : i, x0, y0, lane, t, plane, pa);
             compute(i);
-            stage_store<R, BND>(a, i + 1 < iend ? i + 1 : i, y0, lane, t, s_pl, pa);
+            stage_store_g<R, HALO, PITCH, BND, false>(g, a.k, i + 1 < iend ? i + 1 : i, y0, lane, t, s_pl, pa);
             __syncthreads();
         } else {
-            stage_load<R, BND>(a, i + 2 < iend ? i + 2 : i, x0, y0, lane, t, plane, pa);
+            stage_load_g<R, HALO, PITCH, BND, false>(a.fin, g, a.k, i + 2 < iend ? i + 2 : i, x0, y0, lane, t, plane, pa);
             compute(i);
-            stage_store<R, BND>(a, i + 1, y0, lane, t, s_pl, pb);
+            stage_store_g<R, HALO, PITCH, BND, false>(g, a.k, i + 1, y0, lane, t, s_pl, pb);
             __syncthreads();
-            stage_load<R, BND>(a, i + 3 < iend ? i + 3 : i, x0, y0, lane, t, plane, pb);
+            stage_load_g<R, HALO, PITCH, BND, false>(a.fin, g, a.k, i + 3 < iend ? i + 3 : i, x0, y0, lane, t, plane, pb);
             compute(i + 1);
-            stage_store<R, BND>(a, i + 2 < iend ? i + 2 : i, y0, lane, t, s_pl, pa);
+            stage_store_g<R, HALO, PITCH, BND, false>(g, a.k, i + 2 < iend ? i + 2 : i, y0, lane, t, s_pl, pa);
             __syncthreads();
         }
     }
@@ -425,7 +255,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_
     }
 
     // ---- phase 2 ----
-    const TileMap t = tile_map<R>(a, x0, y0, lane, !interior);
+    const TileMapG t = tile_map_g<R, HALO, false>(grid_of(a), x0, y0, lane, !interior);
     if (interior)
         plane_loop<R, G, false, DEPTH, NT>(a, grp, x0, y0, lane, t, plane, s_pl, s_dx, rho, Tm, uxt,
                                            uyt, t0);

@@ -16,6 +16,7 @@ struct lbm_ctx {
     lbmd::Consts k;                // per-context constants (kernel arguments)
     double* scratch = nullptr;     // 19 planes: ping-pong state of multi-step calls
     double* ke_part = nullptr;     // [ke_cap][2] diagnostic partials
+    double* colbuf = nullptr;      // nx doubles: column sums of lbm_sep_project
 };
 
 int lbmi_validate(const lbm_params* p);
@@ -38,4 +39,12 @@ hipError_t launch_moments(const double* f, double* rho, double* ux, double* uy, 
                           const Consts& k, int64_t n, hipStream_t st);
 hipError_t launch_kinetic_part(const double* f, const Consts& k, int64_t n, double* part,
                                int* nparts, hipStream_t st);
+hipError_t launch_adjoint(const double* f, const double* lam1, double* lam0, const Consts& k,
+                          int nx, int ny, const int bc[4], double cx, double cy, double ct,
+                          double wdxdy, hipStream_t st);
+hipError_t launch_init_vjp(const double* rho, const double* ux, const double* uy, const double* T,
+                           const double* lam, double* grho, double* gux, double* guy, double* gT,
+                           const Consts& k, int64_t n, hipStream_t st);
+hipError_t launch_sep_project(const double* g, const double* A, const double* B, int nx, int ny,
+                              int M, double* col, double* out, hipStream_t st);
 }  // namespace lbmd

@@ -1,0 +1,210 @@
+// lbm_stage.h -- staging of one distribution plane of a 64 x R tile, with a
+// cross-shaped halo of depth H, from global memory into LDS. Shared by the
+// forward and adjoint step kernels of liblbm_hip.
+//
+// The staged image has R+2H rows of PITCH doubles; tile column lx (-H..63+H)
+// sits at lx+H. Every row is one 64-lane load (lane = column 0..63) from a
+// wavefront-uniform row base; the 2H halo columns of the R centre rows come
+// from one more load in which lane l < 2HR takes row l/(2H) and one of the
+// halo columns. A plane costs R+2H+1 loads per lane.
+//
+// Interior tiles (tile plus halo inside the domain) need nothing else. A tile
+// touching the boundary gets a per-lane column map once (source column and
+// kind of the row-load lane and of the halo lane) and resolves ghost rows with
+// uniform logic: a row outside the domain is a periodic wrap, a mirror row of
+// the y-mirrored velocity (reflecting wall), a constant (fixed equilibrium)
+// or unused. Constants and unused slots are substituted when the staged values
+// are written to LDS, so no load result is consumed before it is needed.
+//
+// ZG ("zero ghosts") stages an adjoint field instead: outside the domain it is
+// the periodic image on periodic axes and zero elsewhere, since ghost cells
+// have no update of their own whose adjoint could be non-zero.
+#pragma once
+
+#include "lbm_device.h"
+
+namespace lbmd {
+
+enum { CK_NORM = 0, CK_MIRX = 1, CK_CXLO = 2, CK_CXHI = 3, CK_NONE = 4 };
+enum { RM_NORM = 0, RM_MIRY = 1, RM_CONST = 2, RM_NONE = 3 };
+
+// Boundary description of the grid being staged.
+struct GridBC {
+    int nx, ny;
+    int bc[4];
+};
+
+template <int R, int H, int PITCH>
+struct StageG {
+    static constexpr int ROWS = R + 2 * H;
+    static constexpr int NPRE = ROWS + 1;
+    static constexpr int PAD = ROWS * PITCH;  // 64 pad slots for idle halo lanes
+    static constexpr int SLOTS = PAD + 64;
+    static_assert(2 * H * R <= 64, "the x-halo of the tile must fit one 64-lane load");
+    static_assert(PITCH >= 64 + 2 * H, "row pitch too small");
+};
+
+struct TileMapG {
+    int hrow, hlx;    // halo lane: tile row and column (-H..-1, 64..63+H)
+    int mcol, mkind;  // row-load lane: source column and kind (boundary tiles)
+    int hcol, hkind;  // halo lane: source column and kind (boundary tiles)
+};
+
+// Source column of global column gx for a row inside the domain. Ghost
+// layers deeper than three cells exist only for adjoint staging and only
+// matter on periodic axes (elsewhere the faces that reach them carry no
+// adjoint), so they are unused there.
+template <bool ZG>
+__device__ __forceinline__ void x_source_g(const GridBC& g, int gx, int& col, int& kind)
+{
+    if (gx >= 0 && gx < g.nx) {
+        col = gx;
+        kind = CK_NORM;
+        return;
+    }
+    const bool lo = gx < 0;
+    const int m = lo ? -1 - gx : gx - g.nx;
+    const int bc = lo ? g.bc[XLO] : g.bc[XHI];
+    col = 0;
+    kind = CK_NONE;
+    if (bc == PERIODIC) {
+        col = wrap_index(gx, g.nx);
+        kind = CK_NORM;
+        return;
+    }
+    if (ZG || m >= HALO) return;
+    if (bc == REFLECT) {
+        col = lo ? m : g.nx - 1 - m;
+        kind = CK_MIRX;
+    } else {
+        kind = lo ? CK_CXLO : CK_CXHI;
+    }
+}
+
+template <int R, int H, bool ZG>
+__device__ __forceinline__ TileMapG tile_map_g(const GridBC& g, int x0, int y0, int lane, bool bnd)
+{
+    TileMapG t;
+    const bool hl = lane < 2 * H * R;
+    const int r = lane / (2 * H), c = lane - 2 * H * (lane / (2 * H));
+    t.hrow = hl ? r : 0;
+    t.hlx = hl ? (c < H ? c - H : c + 64 - H) : 0;
+    t.mcol = lane;
+    t.mkind = CK_NORM;
+    t.hcol = 0;
+    t.hkind = CK_NONE;
+    if (bnd) {
+        x_source_g<ZG>(g, x0 + lane, t.mcol, t.mkind);
+        if (hl && y0 + r < g.ny) x_source_g<ZG>(g, x0 + t.hlx, t.hcol, t.hkind);
+    }
+    return t;
+}
+
+// Uniform description of global row gy: mode, source row and side.
+struct RowDesc {
+    int mode, src, side;
+};
+
+template <bool ZG>
+__device__ __forceinline__ RowDesc row_desc_g(const GridBC& g, int gy)
+{
+    RowDesc d{RM_NORM, gy, 0};
+    if (gy >= 0 && gy < g.ny) return d;
+    const bool lo = gy < 0;
+    const int m = lo ? -1 - gy : gy - g.ny;
+    const int bc = lo ? g.bc[YLO] : g.bc[YHI];
+    d.side = lo ? YLO : YHI;
+    d.src = 0;
+    if (bc == PERIODIC) {
+        d.src = wrap_index(gy, g.ny);
+        return d;
+    }
+    d.mode = RM_NONE;
+    if (ZG || m >= HALO) return d;
+    if (bc == REFLECT) {
+        d.mode = RM_MIRY;
+        d.src = lo ? m : g.ny - 1 - m;
+    } else {
+        d.mode = RM_CONST;
+    }
+    return d;
+}
+
+// Issue the loads of plane `i` (base = start of the 19-plane field) into pre.
+template <int R, int H, int PITCH, bool BND, bool ZG>
+__device__ __forceinline__ void stage_load_g(const double* __restrict__ field, const GridBC& g,
+                                             const Consts& k, int i, int x0, int y0, int lane,
+                                             const TileMapG& t, int64_t plane,
+                                             double (&pre)[StageG<R, H, PITCH>::NPRE])
+{
+    using S = StageG<R, H, PITCH>;
+    if (!BND) {
+        const unsigned ul = (unsigned)lane;
+#pragma unroll
+        for (int r = 0; r < S::ROWS; ++r) {
+            const double* row = field + i * plane + (int64_t)(y0 - H + r) * g.nx + x0;
+            pre[r] = row[ul];
+        }
+        // halo columns: offset from column x0 - H so that it is never negative
+        const double* hb = field + i * plane + (int64_t)y0 * g.nx + x0 - H;
+        pre[S::ROWS] = hb[(unsigned)(t.hrow * g.nx + t.hlx + H)];
+    } else {
+        const int64_t pi = i * plane, px = k.mirx[i] * plane, py = k.miry[i] * plane;
+#pragma unroll
+        for (int r = 0; r < S::ROWS; ++r) {
+            const RowDesc d = row_desc_g<ZG>(g, y0 - H + r);
+            int64_t off;
+            if (d.mode == RM_NORM)
+                off = (t.mkind == CK_MIRX ? px : pi) + (int64_t)d.src * g.nx + t.mcol;
+            else if (d.mode == RM_MIRY)
+                off = py + (int64_t)d.src * g.nx + t.mcol;
+            else
+                off = 0;
+            pre[r] = field[off];
+        }
+        const int64_t hoff = t.hkind == CK_NONE
+                                 ? 0
+                                 : (t.hkind == CK_MIRX ? px : pi) + (int64_t)(y0 + t.hrow) * g.nx + t.hcol;
+        pre[S::ROWS] = field[hoff];
+    }
+}
+
+// Write the staged plane `i` to LDS, substituting constants and unused slots.
+template <int R, int H, int PITCH, bool BND, bool ZG>
+__device__ __forceinline__ void stage_store_g(const GridBC& g, const Consts& k, int i, int y0,
+                                              int lane, const TileMapG& t, double* s_pl,
+                                              const double (&pre)[StageG<R, H, PITCH>::NPRE])
+{
+    using S = StageG<R, H, PITCH>;
+    if (!BND) {
+#pragma unroll
+        for (int r = 0; r < S::ROWS; ++r) s_pl[r * PITCH + lane + H] = pre[r];
+    } else {
+        const double cxl = k.side_eq[XLO][i], cxh = k.side_eq[XHI][i];
+#pragma unroll
+        for (int r = 0; r < S::ROWS; ++r) {
+            const RowDesc d = row_desc_g<ZG>(g, y0 - H + r);
+            double v = pre[r];
+            if (d.mode == RM_CONST)
+                v = k.side_eq[d.side][i];
+            else if (d.mode == RM_NONE)
+                v = 0.0;
+            else if (d.mode == RM_NORM)
+                v = t.mkind == CK_CXLO ? cxl
+                    : t.mkind == CK_CXHI ? cxh
+                    : t.mkind == CK_NONE ? 0.0
+                                         : v;
+            s_pl[r * PITCH + lane + H] = v;
+        }
+    }
+    double h = pre[S::ROWS];
+    if (BND)
+        h = t.hkind == CK_CXLO ? k.side_eq[XLO][i]
+            : t.hkind == CK_CXHI ? k.side_eq[XHI][i]
+            : t.hkind == CK_NONE ? 0.0
+                                 : h;
+    const int slot = lane < 2 * H * R ? (t.hrow + H) * PITCH + t.hlx + H : S::PAD + lane;
+    s_pl[slot] = h;
+}
+
+}  // namespace lbmd

@@ -90,6 +90,9 @@ def lib():
         "lbm_step_variant_info": (C.c_int, [_I, C.POINTER(_I)]),
         "lbm_set_step_variant": (C.c_int, [_P, _I]),
         "lbm_get_step_variant": (C.c_int, [_P, C.POINTER(_I)]),
+        "lbm_adjoint_step": (C.c_int, [_P, _P, _P, C.c_double, _P, _P]),
+        "lbm_init_vjp": (C.c_int, [_P] + [_P] * 9 + [_P]),
+        "lbm_sep_project": (C.c_int, [_P, _P, _P, _I, _P, _P, _P]),
         "lbm_last_error": (C.c_char_p, []),
         "lbm_version": (C.c_char_p, []),
     }
@@ -167,6 +170,26 @@ def lbm_moments(h, nx, ny, f, rho, ux, uy, T, stream=None):
 def lbm_kinetic_y(h, nx, ny, f, out2, stream=None):
     _check(lib().lbm_kinetic_y(h, _ptr(f, (NV, ny, nx), "f"), _ptr(out2, (2,), "out2"),
                                _stream(stream)))
+
+
+def lbm_adjoint_step(h, nx, ny, f_n, lam_np1, w, lam_n, stream=None):
+    s = (NV, ny, nx)
+    _check(lib().lbm_adjoint_step(h, _ptr(f_n, s, "f_n"), _ptr(lam_np1, s, "lam_np1"), float(w),
+                                  _ptr(lam_n, s, "lam_n"), _stream(stream)))
+
+
+def lbm_init_vjp(h, nx, ny, rho, ux, uy, T, lam0, g_rho, g_ux, g_uy, g_T, stream=None):
+    s = (ny, nx)
+    _check(lib().lbm_init_vjp(h, _ptr(rho, s, "rho"), _ptr(ux, s, "ux"), _ptr(uy, s, "uy"),
+                              _ptr(T, s, "T"), _ptr(lam0, (NV, ny, nx), "lam0"),
+                              _ptr(g_rho, s, "g_rho"), _ptr(g_ux, s, "g_ux"),
+                              _ptr(g_uy, s, "g_uy"), _ptr(g_T, s, "g_T"), _stream(stream)))
+
+
+def lbm_sep_project(h, nx, ny, g, A, B, out, stream=None):
+    M = int(A.shape[0])
+    _check(lib().lbm_sep_project(h, _ptr(g, (ny, nx), "g"), _ptr(A, (M, nx), "A"), M,
+                                 _ptr(B, (ny,), "B"), _ptr(out, (M,), "out"), _stream(stream)))
 
 
 def lbm_step_variant_count():
@@ -248,6 +271,23 @@ class Context:
     def kinetic_y(self, f):
         out = torch.empty(2, dtype=torch.float64, device=self.device)
         lbm_kinetic_y(self.handle, self.nx, self.ny, f, out)
+        return out
+
+    def adjoint_step(self, f_n, lam_np1, w=0.0, out=None):
+        out = self.empty_f() if out is None else out
+        lbm_adjoint_step(self.handle, self.nx, self.ny, f_n, lam_np1, w, out)
+        return out
+
+    def init_vjp(self, rho, ux, uy, T, lam0):
+        outs = [self.empty_plane() for _ in range(4)]
+        lbm_init_vjp(self.handle, self.nx, self.ny, *(self._dev(x) for x in (rho, ux, uy, T)),
+                     lam0, *outs)
+        return tuple(outs)
+
+    def sep_project(self, g, A, B):
+        A = self._dev(A)
+        out = torch.empty(A.shape[0], dtype=torch.float64, device=self.device)
+        lbm_sep_project(self.handle, self.nx, self.ny, g, A, self._dev(B), out)
         return out
 
     @property
