@@ -150,6 +150,73 @@ int lbm_step_variant_info(int32_t variant, int32_t* info5);
 int lbm_set_step_variant(lbm_ctx* ctx, int32_t variant);
 int lbm_get_step_variant(lbm_ctx* ctx, int32_t* variant);
 
+/* ---- Batches of independent grids -------------------------------------
+ *
+ * A batch advances n independent grids ("instances") of possibly different
+ * sizes, boundary rules, dx, dy, dt, tau and fixed-side states by the same
+ * forward step as lbm_step, all instances in each launch: the work items of
+ * every instance form one list that one kernel launch covers. Instances must
+ * share vk and weno_eps (they share the velocity set and weights).
+ *
+ * Layout. A batch distribution field holds instance i's 19-plane field
+ * ([19][ny_i][nx_i], as above) at element offset f_offset[i]; blocks must not
+ * overlap (gaps are allowed and left untouched). The field's extent is
+ * max_i (f_offset[i] + 19 nx_i ny_i) elements (lbm_batch_info). A batch
+ * scalar field packs the instances back to back in instance order: instance
+ * i's plane starts at element sum_{j<i} nx_j ny_j.
+ */
+typedef struct lbm_batch lbm_batch;
+
+/* Validate the n >= 1 parameter sets and create a batch on the current
+ * device. f_offset: host int64[n], or NULL for back-to-back packing in
+ * instance order. Allocates one ping-pong field of the batch's extent,
+ * per-tile partials, the device descriptor table and the work list, and a
+ * private stream used only to capture graphs. Synchronous.
+ * Errors: LBM_EINVAL (invalid instance, differing vk or weno_eps,
+ * overlapping or negative offsets), LBM_EUNSUPPORTED, LBM_ENOMEM, LBM_EHIP. */
+int lbm_batch_create(const lbm_params* inst, int32_t n, const int64_t* f_offset,
+                     lbm_batch** out);
+
+/* Free a batch, its captured graphs and device buffers (synchronises the
+ * device). NULL is a no-op. */
+void lbm_batch_destroy(lbm_batch* b);
+
+/* out4 (host int64[4]) = (n, extent of a batch distribution field in
+ * elements, total cells = length of a batch scalar field, work items per
+ * launch of the current variant). */
+int lbm_batch_info(lbm_batch* b, int64_t* out4);
+
+/* lbm_init for every instance: batch scalar fields in, batch field out. */
+int lbm_batch_init(lbm_batch* b, const double* rho, const double* ux, const double* uy,
+                   const double* T, double* f_out, lbm_stream stream);
+
+/* lbm_moments for every instance: batch field in, batch scalar fields out. */
+int lbm_batch_moments(lbm_batch* b, const double* f, double* rho, double* ux, double* uy,
+                      double* T, lbm_stream stream);
+
+/* lbm_step for every instance (Eq. (47)), nsteps >= 1, f_in unchanged, the
+ * result in f_out. ke_log: NULL, or device double[n * nsteps * 2] with
+ * ke_log[(i*nsteps + s)*2 + 0/1] = (sum_cells rho u_y^2/2 dx dy, max_cells
+ * rho u_y^2/2) of instance i in the state step s starts from. Each instance's
+ * result is identical to lbm_step's for that instance alone with the same
+ * variant. With a graph chunk C set (lbm_batch_set_schedule), steps after the
+ * first run as replays of a captured graph of C steps (cached per buffer
+ * pair; recaptured when the variant, the schedule or the buffers change). */
+int lbm_batch_step(lbm_batch* b, const double* f_in, double* f_out, int32_t nsteps,
+                   double* ke_log, lbm_stream stream);
+
+/* Step variant of the batch kernel (same table as lbm_step_variant_info).
+ * Setting it rebuilds the device work list (synchronises the device). */
+int lbm_batch_set_step_variant(lbm_batch* b, int32_t variant);
+int lbm_batch_get_step_variant(lbm_batch* b, int32_t* variant);
+
+/* Launch schedule. slots_per_xcd = 0: one workgroup per work item; s > 0:
+ * a persistent grid of 8 s workgroups, each looping over its XCD's band of
+ * the work list. graph_chunk = 0: one launch per step; an even C >= 2:
+ * graph replays of C steps. out2 = (slots_per_xcd, graph_chunk). */
+int lbm_batch_set_schedule(lbm_batch* b, int32_t slots_per_xcd, int32_t graph_chunk);
+int lbm_batch_get_schedule(lbm_batch* b, int32_t* out2);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* lbm_last_error(void);
 

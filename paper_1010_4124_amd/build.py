@@ -1,8 +1,8 @@
 """Build liblbm_hip.so in-tree for gfx950 with hipcc.
 
-Every HIP translation unit under csrc/ is compiled into one shared library
-next to this file. Packed FP32 instructions are switched off
-(-packed-fp32-ops); the hot path is FP64 anyway.
+Every HIP translation unit under csrc/ is compiled (in parallel) and linked
+into one shared library next to this file. Packed FP32 instructions are
+switched off (-packed-fp32-ops); the hot path is FP64 anyway.
 """
 from __future__ import annotations
 
@@ -10,6 +10,8 @@ import glob
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -26,20 +28,43 @@ def headers():
                   glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
-def build(verbose: bool = False) -> str:
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc, "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Wall", "-Wno-unused-result",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           *sources(), "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building liblbm_hip.so")
+    return r.returncode
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every translation unit (in parallel) and link liblbm_hip.so."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    # The kernels take their constants as one large by-value argument and
+    # index it at run time; the front end copies such an argument to the
+    # stack and the optimiser forwards the loads to the argument segment only
+    # if the copy has at most instcombine-max-copied-from-constant-users
+    # users (default 300), so the limit is raised to keep every kernel free
+    # of that scratch copy.
+    flags = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+             "-mllvm", "-instcombine-max-copied-from-constant-users=100000",
+             "-Wall", "-Wno-unused-result",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+    with tempfile.TemporaryDirectory(prefix="lbm_build_") as tmpd:
+        objs, cmds = [], []
+        for src in sources():
+            obj = os.path.join(tmpd, os.path.basename(src) + ".o")
+            objs.append(obj)
+            cmds.append([hipcc, *flags, "-c", src, "-o", obj])
+        jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+        with ThreadPoolExecutor(jobs) as ex:
+            codes = list(ex.map(lambda c: _run(c, verbose), cmds))
+        if any(codes):
+            raise RuntimeError("hipcc failed compiling liblbm_hip sources")
+        tmp = LIB + ".tmp%d" % os.getpid()
+        if _run([hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp], verbose):
+            raise RuntimeError("hipcc failed linking liblbm_hip.so")
     os.replace(tmp, LIB)
     return LIB
 

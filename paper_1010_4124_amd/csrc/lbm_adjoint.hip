@@ -176,6 +176,7 @@ __device__ __forceinline__ void adj_planes(const AdjArgs& a, int x0, int y0, int
     using SF = StageG<R, FH, AP>;
     using SL = StageG<R, LH, AP>;
     const GridBC g = grid_of(a);
+    const SideEqConsts se{};
     const int64_t plane = (int64_t)a.nx * a.ny;
     const int gx = x0 + lane;
     const double omct = 1.0 - a.ct, eps = a.k.eps;
@@ -188,8 +189,8 @@ __device__ __forceinline__ void adj_planes(const AdjArgs& a, int x0, int y0, int
         double pf[SF::NPRE], pl[SL::NPRE];
         stage_load_g<R, FH, AP, BND, false>(a.f, g, a.k, i, x0, y0, lane, tf, plane, pf);
         stage_load_g<R, LH, AP, BND, true>(a.lam1, g, a.k, i, x0, y0, lane, tl, plane, pl);
-        stage_store_g<R, FH, AP, BND, false>(g, a.k, i, y0, lane, tf, s_f, pf);
-        stage_store_g<R, LH, AP, BND, true>(g, a.k, i, y0, lane, tl, s_l, pl);
+        stage_store_g<R, FH, AP, BND, false>(g, a.k, se, i, y0, lane, tf, s_f, pf);
+        stage_store_g<R, LH, AP, BND, true>(g, a.k, se, i, y0, lane, tl, s_l, pl);
         __syncthreads();
         const double vx = a.k.vx[i], vy = a.k.vy[i];
         {  // x strips: lane -> (row r = lane % R, strip s = lane / R)

@@ -33,6 +33,8 @@ int hip_fail(hipError_t e, const char* where)
 
 const char* lbm_last_error(void) { return g_err.c_str(); }
 
+void lbmi_set_error(const char* msg) { g_err = msg; }
+
 const char* lbm_version(void) { return "lbm_hip 0.1 gfx950 d2v19-weno5"; }
 
 int lbmi_validate(const lbm_params* p)
@@ -251,13 +253,14 @@ int lbm_get_step_variant(lbm_ctx* c, int32_t* v)
     return LBM_OK;
 }
 
-// Default step variant (the autotuner can override it per context): on large
-// grids one velocity group with two planes in flight and non-temporal
+// Default step variant (the autotuner can override it per context or batch):
+// on large grids (or batches) one velocity group with two planes in flight and non-temporal
 // stores; on small grids three velocity groups, so that there are enough
 // workgroups for all 256 CUs.
-int lbmi_default_variant(int nx, int ny)
+int lbmi_default_variant(int nx, int ny) { return lbmi_default_variant_cells((int64_t)nx * ny); }
+
+int lbmi_default_variant_cells(int64_t cells)
 {
-    const long long cells = (long long)nx * ny;
     const int want[5] = {4, cells >= (1ll << 21) ? 1 : 3, 3, cells >= (1ll << 21) ? 2 : 1,
                          cells >= (1ll << 21) ? 1 : 0};
     for (int v = 0; v < step_variant_count(); ++v) {

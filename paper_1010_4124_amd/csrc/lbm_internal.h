@@ -22,6 +22,8 @@ struct lbm_ctx {
 int lbmi_validate(const lbm_params* p);
 void lbmi_fill_consts(const lbm_params* p, lbmd::Consts* h);
 int lbmi_default_variant(int nx, int ny);
+int lbmi_default_variant_cells(int64_t cells);
+void lbmi_set_error(const char* msg);
 
 namespace lbmd {
 int step_variant_count();

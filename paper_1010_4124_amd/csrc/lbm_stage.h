@@ -169,9 +169,30 @@ __device__ __forceinline__ void stage_load_g(const double* __restrict__ field, c
     }
 }
 
-// Write the staged plane `i` to LDS, substituting constants and unused slots.
-template <int R, int H, int PITCH, bool BND, bool ZG>
-__device__ __forceinline__ void stage_store_g(const GridBC& g, const Consts& k, int i, int y0,
+// Fixed-equilibrium ghost values of a context, held in its by-value
+// constants. Stateless on purpose: a functor holding a pointer to by-value
+// kernel arguments makes the compiler copy them to scratch memory.
+struct SideEqConsts {
+    __device__ __forceinline__ double operator()(const Consts& k, int side, int i) const
+    {
+        return k.side_eq[side][i];
+    }
+};
+
+// Fixed-equilibrium ghost values read from global memory laid out [4][NV].
+struct SideEqPtr {
+    const double* p;
+    __device__ __forceinline__ double operator()(const Consts&, int side, int i) const
+    {
+        return p[side * NV + i];
+    }
+};
+
+// Write the staged plane `i` to LDS, substituting constants and unused slots;
+// se(k, side, i) gives the fixed-equilibrium ghost value of velocity i on a
+// side.
+template <int R, int H, int PITCH, bool BND, bool ZG, class SE>
+__device__ __forceinline__ void stage_store_g(const GridBC& g, const Consts& k, SE se, int i, int y0,
                                               int lane, const TileMapG& t, double* s_pl,
                                               const double (&pre)[StageG<R, H, PITCH>::NPRE])
 {
@@ -180,13 +201,13 @@ __device__ __forceinline__ void stage_store_g(const GridBC& g, const Consts& k, 
 #pragma unroll
         for (int r = 0; r < S::ROWS; ++r) s_pl[r * PITCH + lane + H] = pre[r];
     } else {
-        const double cxl = k.side_eq[XLO][i], cxh = k.side_eq[XHI][i];
+        const double cxl = se(k, XLO, i), cxh = se(k, XHI, i);
 #pragma unroll
         for (int r = 0; r < S::ROWS; ++r) {
             const RowDesc d = row_desc_g<ZG>(g, y0 - H + r);
             double v = pre[r];
             if (d.mode == RM_CONST)
-                v = k.side_eq[d.side][i];
+                v = se(k, d.side, i);
             else if (d.mode == RM_NONE)
                 v = 0.0;
             else if (d.mode == RM_NORM)
@@ -199,8 +220,8 @@ __device__ __forceinline__ void stage_store_g(const GridBC& g, const Consts& k, 
     }
     double h = pre[S::ROWS];
     if (BND)
-        h = t.hkind == CK_CXLO ? k.side_eq[XLO][i]
-            : t.hkind == CK_CXHI ? k.side_eq[XHI][i]
+        h = t.hkind == CK_CXLO ? se(k, XLO, i)
+            : t.hkind == CK_CXHI ? se(k, XHI, i)
             : t.hkind == CK_NONE ? 0.0
                                  : h;
     const int slot = lane < 2 * H * R ? (t.hrow + H) * PITCH + t.hlx + H : S::PAD + lane;

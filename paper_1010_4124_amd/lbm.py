@@ -93,6 +93,17 @@ def lib():
         "lbm_adjoint_step": (C.c_int, [_P, _P, _P, C.c_double, _P, _P]),
         "lbm_init_vjp": (C.c_int, [_P] + [_P] * 9 + [_P]),
         "lbm_sep_project": (C.c_int, [_P, _P, _P, _I, _P, _P, _P]),
+        "lbm_batch_create": (C.c_int, [C.POINTER(LbmParams), _I, C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_void_p)]),
+        "lbm_batch_destroy": (None, [_P]),
+        "lbm_batch_info": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+        "lbm_batch_init": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+        "lbm_batch_moments": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+        "lbm_batch_step": (C.c_int, [_P, _P, _P, _I, _P, _P]),
+        "lbm_batch_set_step_variant": (C.c_int, [_P, _I]),
+        "lbm_batch_get_step_variant": (C.c_int, [_P, C.POINTER(_I)]),
+        "lbm_batch_set_schedule": (C.c_int, [_P, _I, _I]),
+        "lbm_batch_get_schedule": (C.c_int, [_P, C.POINTER(_I)]),
         "lbm_last_error": (C.c_char_p, []),
         "lbm_version": (C.c_char_p, []),
     }
@@ -212,6 +223,175 @@ def lbm_get_step_variant(h):
     v = _I()
     _check(lib().lbm_get_step_variant(h, C.byref(v)))
     return v.value
+
+
+# --- batches -------------------------------------------------------------------
+def lbm_batch_create(params, f_offset=None):
+    """params: sequence of LbmParams; f_offset: None or int sequence."""
+    _require_gpu()
+    n = len(params)
+    arr = (LbmParams * n)(*params)
+    offs = None if f_offset is None else (C.c_int64 * n)(*[int(o) for o in f_offset])
+    h = C.c_void_p()
+    _check(lib().lbm_batch_create(arr, n, offs, C.byref(h)))
+    return h
+
+
+def lbm_batch_destroy(h):
+    if h:
+        lib().lbm_batch_destroy(h)
+
+
+def lbm_batch_info(h):
+    """(n, field extent, total cells, work items per launch)."""
+    out = (C.c_int64 * 4)()
+    _check(lib().lbm_batch_info(h, out))
+    return tuple(int(x) for x in out)
+
+
+def _flat(t, n, what):
+    if t is not None and t.dim() != 1:
+        raise ValueError(f"{what} must be 1-d")
+    return _ptr(t, (n,), what)
+
+
+def lbm_batch_init(h, rho, ux, uy, T, f_out, stream=None):
+    _, ext, cells, _ = lbm_batch_info(h)
+    _check(lib().lbm_batch_init(h, _flat(rho, cells, "rho"), _flat(ux, cells, "ux"),
+                                _flat(uy, cells, "uy"), _flat(T, cells, "T"),
+                                _flat(f_out, ext, "f_out"), _stream(stream)))
+
+
+def lbm_batch_moments(h, f, rho, ux, uy, T, stream=None):
+    _, ext, cells, _ = lbm_batch_info(h)
+    _check(lib().lbm_batch_moments(h, _flat(f, ext, "f"), _flat(rho, cells, "rho"),
+                                   _flat(ux, cells, "ux"), _flat(uy, cells, "uy"),
+                                   _flat(T, cells, "T"), _stream(stream)))
+
+
+def lbm_batch_step(h, f_in, f_out, nsteps=1, ke_log=None, stream=None):
+    n, ext, _, _ = lbm_batch_info(h)
+    if ke_log is not None:
+        _ptr(ke_log, (n, int(nsteps), 2), "ke_log")
+    _check(lib().lbm_batch_step(h, _flat(f_in, ext, "f_in"), _flat(f_out, ext, "f_out"),
+                                int(nsteps), _ptr(ke_log), _stream(stream)))
+
+
+def lbm_batch_set_step_variant(h, v):
+    _check(lib().lbm_batch_set_step_variant(h, int(v)))
+
+
+def lbm_batch_get_step_variant(h):
+    v = _I()
+    _check(lib().lbm_batch_get_step_variant(h, C.byref(v)))
+    return v.value
+
+
+def lbm_batch_set_schedule(h, slots_per_xcd=0, graph_chunk=0):
+    _check(lib().lbm_batch_set_schedule(h, int(slots_per_xcd), int(graph_chunk)))
+
+
+def lbm_batch_get_schedule(h):
+    out = (_I * 2)()
+    _check(lib().lbm_batch_get_schedule(h, out))
+    return int(out[0]), int(out[1])
+
+
+class Batch:
+    """Owns one lbm_batch* over instances given as LbmParams or Setups.
+
+    Batch distribution fields are flat float64 tensors of ``extent`` elements
+    (instance i's [19][ny][nx] block at ``offsets[i]``); batch scalar fields
+    are flat tensors of ``cells`` elements packing the instances in order."""
+
+    def __init__(self, params, f_offset=None):
+        self.params = list(params)
+        self.handle = lbm_batch_create(self.params, f_offset)
+        self.n, self.extent, self.cells, _ = lbm_batch_info(self.handle)
+        self.shapes = [(int(p.nx), int(p.ny)) for p in self.params]
+        if f_offset is None:
+            f_offset, o = [], 0
+            for nx, ny in self.shapes:
+                f_offset.append(o)
+                o += NV * nx * ny
+        self.offsets = [int(o) for o in f_offset]
+        self.cell_offsets, c = [], 0
+        for nx, ny in self.shapes:
+            self.cell_offsets.append(c)
+            c += nx * ny
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    @classmethod
+    def from_setups(cls, setups, f_offset=None):
+        return cls([LbmParams.make(s.nx, s.ny, s.dx, s.dy, s.dt, s.tau, s.bc,
+                                   side_state=s.side_state) for s in setups], f_offset)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lbm_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty_f(self):
+        return torch.empty(self.extent, dtype=torch.float64, device=self.device)
+
+    def empty_scalar(self):
+        return torch.empty(self.cells, dtype=torch.float64, device=self.device)
+
+    def view(self, f, i):
+        """Instance i's (19, ny, nx) view of a batch field."""
+        nx, ny = self.shapes[i]
+        o = self.offsets[i]
+        return f[o:o + NV * nx * ny].view(NV, ny, nx)
+
+    def scalar_view(self, a, i):
+        nx, ny = self.shapes[i]
+        o = self.cell_offsets[i]
+        return a[o:o + nx * ny].view(ny, nx)
+
+    def pack_scalars(self, planes):
+        """Concatenate per-instance (ny, nx) planes into one batch scalar field."""
+        return torch.cat([torch.as_tensor(p, dtype=torch.float64).reshape(-1) for p in planes]).to(
+            self.device).contiguous()
+
+    def init(self, rho, ux, uy, T, out=None):
+        out = self.empty_f() if out is None else out
+        lbm_batch_init(self.handle, rho, ux, uy, T, out)
+        return out
+
+    def step(self, f, nsteps=1, out=None, ke_log=False):
+        out = self.empty_f() if out is None else out
+        ke = (torch.empty((self.n, int(nsteps), 2), dtype=torch.float64, device=self.device)
+              if ke_log else None)
+        lbm_batch_step(self.handle, f, out, nsteps, ke)
+        return (out, ke) if ke_log else out
+
+    def moments(self, f):
+        outs = [self.empty_scalar() for _ in range(4)]
+        lbm_batch_moments(self.handle, f, *outs)
+        return tuple(outs)
+
+    @property
+    def variant(self):
+        return lbm_batch_get_step_variant(self.handle)
+
+    @variant.setter
+    def variant(self, v):
+        lbm_batch_set_step_variant(self.handle, v)
+
+    @property
+    def schedule(self):
+        """(persistent workgroups per XCD or 0, graph chunk or 0)."""
+        return lbm_batch_get_schedule(self.handle)
+
+    @schedule.setter
+    def schedule(self, sc):
+        lbm_batch_set_schedule(self.handle, *sc)
 
 
 # --- convenience owner -------------------------------------------------------

@@ -51,3 +51,33 @@ def test_create_rejects_bad_params_without_gpu():
     p = lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5, bc=(3, 3, 0, 0))
     h = C.c_void_p()
     assert L.lbm_create(C.byref(p), C.byref(h)) == lbm.LBM_EUNSUPPORTED
+
+
+def test_batch_create_rejects_bad_instances_without_gpu():
+    """Batch validation (instances, shared vk and eps, offsets) happens before
+    any device work."""
+    import ctypes as C
+    L = lbm.lib()
+
+    def create(ps, offs=None):
+        arr = (lbm.LbmParams * len(ps))(*ps)
+        o = None if offs is None else (C.c_int64 * len(ps))(*offs)
+        h = C.c_void_p()
+        return L.lbm_batch_create(arr, len(ps), o, C.byref(h))
+
+    good = lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5)
+    other_vk = lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5, vk=(1.0, 2.0, 3.5))
+    other_eps = lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5, eps=1e-7)
+    bad = lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 0.0)
+    outflow = lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5, bc=(3, 3, 0, 0))
+    h = C.c_void_p()
+    assert L.lbm_batch_create(None, 1, None, C.byref(h)) == lbm.LBM_EINVAL
+    assert create([good, other_vk]) == lbm.LBM_EINVAL
+    assert create([good, other_eps]) == lbm.LBM_EINVAL
+    assert create([good, bad]) == lbm.LBM_EINVAL
+    assert create([good, outflow]) == lbm.LBM_EUNSUPPORTED
+    n = 19 * 64
+    assert create([good, good], [0, n - 1]) == lbm.LBM_EINVAL     # overlapping blocks
+    assert create([good, good], [n, 0 + 5]) == lbm.LBM_EINVAL     # overlapping, reversed
+    assert create([good, good], [-1, n]) == lbm.LBM_EINVAL        # negative offset
+    assert b"overlap" in L.lbm_last_error()
