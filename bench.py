@@ -5,137 +5,417 @@ convection of all 18 moving velocities along x and y, BGK relaxation,
 update) of the single shear-layer workload: 512 x 512 cells, periodic in x,
 reflecting walls in y, dx = dy = 1e-3, dt = tau = 1e-5, D_v = D_rho = 0.02,
 20000 steps. Inputs are seeded synthetic fields already resident in HBM when
-the timed region starts.
+the timed region starts; the step variant is chosen by the autotuner before
+it.
 
 Prints one JSON line. `value` is MLUPS (million lattice-site updates per
-second) of that run; `roofline` relates the step kernel's algorithmic HBM
-traffic (19 FP64 values read + 19 written = 304 B per site update) to the
-8 TB/s HBM3E peak; `cpu_baseline` is the CPU oracle timed on a bounded sample
-of the same workload on this host.
+second) of the timed run. `roofline` relates the step kernel's algorithmic
+HBM traffic (19 FP64 values read + 19 written = 304 B per site update) to the
+8 TB/s HBM3E peak, over the kernel's average launch duration: HIP events on
+the stream the kernel runs on bracket the timed region, which holds exactly
+`steps` launches of the step kernel and nothing else; `traffic` is the
+measured HBM traffic per launch from the committed rocprofv3 counter summary
+when it was taken on the current kernel sources. `extra` holds the other
+workloads: the 2048^2 forward step, the adjoint (reverse step alone and the
+full checkpointed gradient) and the 64-instance batched sweep. `cpu_baseline`
+is the CPU oracle timed on a bounded sample of the main workload.
+
+Other modes (for the rocprofv3 runs whose summaries live in profiles/):
+  --pmc-run        a few steps of the main workload plus a 512 MiB device
+                   copy, for one counter pass
+  --summarize ...  turn the kernel-trace and counter CSVs into the summary
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
+import re
+import statistics
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-BYTES_PER_LUP = 19 * 8 * 2
+BYTES_PER_LUP = 19 * 8 * 2          # forward: f^n read once, f^{n+1} written once
+ADJ_BYTES_PER_LUP = 19 * 8 * 3      # adjoint: f^n and lambda^{n+1} read, lambda^n written
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 512 << 20              # reference copy for the counter scale factors
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_khi512_counters.md")
+METRIC = "MLUPS (D2V19+WENO5, FP64) fwd/adjoint/batched + % HBM roofline"
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def time_forward(ctx, f0, steps, warmup):
+def source_hash():
+    """Hash of the kernel sources: counter summaries apply only to these."""
+    h = hashlib.sha1()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1010_4124_amd", "csrc", "*")) +
+                   [os.path.join(ROOT, "paper_1010_4124_amd", "build.py")])
+    for p in files:
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def main_setup():
+    from paper_1010_4124_amd import inputs
+    return inputs.khi(512, 512, dx=1e-3, dy=1e-3, dt=1e-5, tau=1e-5, Dv=0.02, Drho=0.02)
+
+
+def sync_time(fn):
     import torch
-    fa = ctx.empty_f()
-    if warmup:
-        ctx.step(f0, warmup, out=fa)
-    torch.cuda.synchronize()
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
     e0.record(st)
-    ctx.step(f0, steps, out=fa)
+    fn()
     e1.record(st)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / 1e3, fa
+    return e0.elapsed_time(e1) / 1e3, time.perf_counter() - w0
 
 
-def cpu_baseline(setup, nsteps):
+def read_traffic(kernel_name):
+    """HBM bytes per launch from the committed counter summary, or None when
+    it is missing, was taken on other sources, or on another kernel."""
+    try:
+        txt = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    m_hash = re.search(r"source_sha1:\s*(\w+)", txt)
+    m_kern = re.search(r"kernel:\s*(.+)", txt)
+    m_traf = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not (m_hash and m_kern and m_traf):
+        return None
+    if m_hash.group(1) != source_hash() or m_kern.group(1).strip() != kernel_name:
+        return None
+    return float(m_traf.group(1))
+
+
+def step_kernel_name(variant):
+    from paper_1010_4124_amd import lbm
+    R, G, W, D, NT = lbm.lbm_step_variant_info(variant)
+    return f"lbmd::k_step<{R}, {G}, {W}, {D}, {'true' if NT else 'false'}>"
+
+
+# ---------------------------------------------------------------------------
+def bench_forward_main(args):
+    import torch
+    from paper_1010_4124_amd import lbm, tune
+    s = main_setup()
+    ctx = lbm.Context.from_setup(s)
+    f0 = ctx.init(*s.fields())
+    if args.variant is None:
+        t = tune.tune_context(ctx, f0, use_cache=False)
+        how = f"tuned, ms/step {min(t['ms'].values()):.4f}"
+    else:
+        ctx.variant = args.variant
+        how = "fixed by --variant"
+    log(f"forward 512^2: variant {ctx.variant} {lbm.lbm_step_variant_info(ctx.variant)} ({how})")
+    out = ctx.empty_f()
+    if args.warmup:
+        ctx.step(f0, args.warmup, out=out)
+    secs, wall = sync_time(lambda: ctx.step(f0, args.steps, out=out))
+    lups = s.nx * s.ny * args.steps
+    if not torch.isfinite(ctx.moments(out)[0]).all():
+        raise SystemExit("non-finite state after the timed run")
+    avg = secs / args.steps  # the timed region holds exactly these step launches
+    log(f"forward 512^2: {lups / secs / 1e6:.1f} MLUPS ({secs:.3f} s events, {wall:.3f} s wall), "
+        f"{avg * 1e6:.2f} us per launch")
+    return s, ctx, f0, secs, wall, avg
+
+
+def bench_forward_large(args):
+    from paper_1010_4124_amd import inputs, lbm, tune
+    big = inputs.khi(2048, 2048, dx=1e-3, dy=1e-3, dt=1e-5, tau=1e-5, Dv=0.01, Drho=0.04)
+    ctx = lbm.Context.from_setup(big)
+    f0 = ctx.init(*big.fields())
+    tune.tune_context(ctx, f0, nsteps=10, use_cache=False)
+    out = ctx.empty_f()
+    ctx.step(f0, 10, out=out)
+    secs, _ = sync_time(lambda: ctx.step(f0, args.large_steps, out=out))
+    lups = big.nx * big.ny * args.large_steps
+    r = {"MLUPS": lups / secs / 1e6, "steps": args.large_steps,
+         "variant": list(lbm.lbm_step_variant_info(ctx.variant)),
+         "us_per_step": secs / args.large_steps * 1e6,
+         "hbm_frac": BYTES_PER_LUP * lups / secs / 1e9 / HBM_PEAK_GBS}
+    log(f"forward 2048^2: {r}")
+    return r
+
+
+def bench_adjoint(args):
+    import torch
+    from paper_1010_4124_amd import inputs, lbm, objective
+    res = {}
+    # reverse step alone at 256^2 and 2048^2
+    for n, steps in ((256, 200), (2048, 20)):
+        s = inputs.khi(n, n, Dv=0.02, Drho=0.02)
+        ctx = lbm.Context.from_setup(s)
+        f0 = ctx.init(*s.fields())
+        lam = [torch.zeros_like(f0), ctx.empty_f()]
+
+        def run():
+            for q in range(steps):
+                ctx.adjoint_step(f0, lam[q % 2], 1e-5, out=lam[(q + 1) % 2])
+        run()
+        secs, _ = sync_time(run)
+        mlups = n * n * steps / secs / 1e6
+        res[f"reverse_step_{n}"] = {"MLUPS": mlups,
+                                    "hbm_frac": mlups * 1e6 * ADJ_BYTES_PER_LUP / 1e9 / HBM_PEAK_GBS}
+        del ctx, f0, lam
+        torch.cuda.empty_cache()
+    # full checkpointed gradient, 256^2 shear layer, 4000 steps, checkpoints every 200
+    rng_amps = inputs.mode_amplitudes(256, seed=7)
+    prob = objective.KHIProblem(256, 256, nsteps=args.adj_steps,
+                                window=(args.adj_steps // 2, args.adj_steps),
+                                schedule=objective.Schedule.every(200))
+    fwd_secs, _ = sync_time(lambda: prob.run(0.02, 0.02, rng_amps))
+    J, ck = prob.run(0.02, 0.02, rng_amps)
+    grad_secs, _ = sync_time(lambda: prob.gradient(0.02, 0.02, rng_amps, ck=ck))
+    lups = 256 * 256 * args.adj_steps
+    res["gradient_256"] = {"steps": args.adj_steps, "checkpoint_every": 200,
+                           "forward_MLUPS": lups / fwd_secs / 1e6,
+                           "adjoint_MLUPS": lups / grad_secs / 1e6,
+                           "note": "adjoint = recompute + reverse, per forward step"}
+    # 2048^2, sqrt-N two-level schedule over a bounded number of steps
+    n2 = args.adj_large_steps
+    prob2 = objective.KHIProblem(2048, 2048, nsteps=n2, window=(n2 // 2, n2),
+                                 schedule=objective.Schedule.sqrt(n2))
+    amps2 = inputs.mode_amplitudes(2048, seed=7)
+    fsecs, _ = sync_time(lambda: prob2.run(0.01, 0.04, amps2, keep_checkpoints=False))
+    J2, ck2 = prob2.run(0.01, 0.04, amps2)
+    gsecs, _ = sync_time(lambda: prob2.gradient(0.01, 0.04, amps2, ck=ck2))
+    l2 = 2048 * 2048 * n2
+    res["gradient_2048"] = {"steps": n2, "schedule": [prob2.schedule.K1, prob2.schedule.K2],
+                            "forward_MLUPS": l2 / fsecs / 1e6, "adjoint_MLUPS": l2 / gsecs / 1e6}
+    log(f"adjoint: {res}")
+    del prob, prob2, ck, ck2
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_batch(args):
+    import numpy as np
+    import torch
+    from paper_1010_4124_amd import growth, inputs, lbm, tune
+    draw = inputs.batch_draw(2024, n=64)
+    setups = [inputs.khi(d["nx"], d["ny"], Dv=d["Dv"], Drho=d["Drho"]) for d in draw]
+    b = lbm.Batch.from_setups(setups)
+    fields = [s.fields() for s in setups]
+    f0 = b.init(*[b.pack_scalars([f[q] for f in fields]) for q in range(4)])
+    tune.tune_batch(b, f0, slots=(0, 384), use_cache=False)
+    b.schedule = (b.schedule[0], 100)
+    out = b.empty_f()
+    ke = torch.empty((b.n, args.batch_steps, 2), dtype=torch.float64, device=out.device)
+    lbm.lbm_batch_step(b.handle, f0, out, 100, ke[:, :100].contiguous())  # warm: capture graph
+    secs, _ = sync_time(lambda: lbm.lbm_batch_step(b.handle, f0, out, args.batch_steps, ke))
+    kel = ke.cpu().numpy()
+    gam, below = [], 0
+    for i, (d, s) in enumerate(zip(draw, setups)):
+        try:
+            g, _ = growth.growth_rate(kel[i], s.dt)
+        except ValueError:
+            continue
+        gam.append(g)
+        below += g < growth.classical_rate(d["nx"] * s.dx)
+    r = {"instances": b.n, "cells": b.cells, "steps": args.batch_steps,
+         "MLUPS": b.cells * args.batch_steps / secs / 1e6,
+         "variant": list(lbm.lbm_step_variant_info(b.variant)), "slots_per_xcd": b.schedule[0],
+         "graph_chunk": b.schedule[1], "ke_logged": True,
+         "gamma": {"fitted": len(gam), "median": float(np.median(gam)) if gam else None,
+                   "min": float(np.min(gam)) if gam else None,
+                   "max": float(np.max(gam)) if gam else None, "below_classical": int(below)}}
+    log(f"batched sweep: {r}")
+    return r
+
+
+def cpu_baseline(setup, seconds):
     import oracle
     p = oracle.OracleParams.make(setup.nx, setup.ny, setup.dx, setup.dy, setup.dt, setup.tau,
                                  setup.bc)
-    f0 = oracle.init(p, *setup.fields())
+    f = oracle.init(p, *setup.fields())
     threads = min(16, os.cpu_count() or 1)
-    t = time.perf_counter()
-    oracle.step(p, f0, nsteps, nthreads=threads)
-    dt = time.perf_counter() - t
-    return {"value": setup.nx * setup.ny * nsteps / dt / 1e6, "unit": "MLUPS", "cores": threads,
+    steps, chunk = 0, 10
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds and steps < 5000:
+        f = oracle.step(p, f, chunk, nthreads=threads)
+        steps += chunk
+    dt = time.perf_counter() - t0
+    return {"value": setup.nx * setup.ny * steps / dt / 1e6, "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
-            "sample": f"{setup.nx}x{setup.ny} shear layer, {nsteps} steps from the same "
-                      f"initial state ({dt:.1f} s)"}
+            "sample": f"{setup.nx}x{setup.ny} shear layer (the main workload), first {steps} "
+                      f"of its steps from the same initial state, {dt:.1f} s on {threads} threads"}
 
 
+# ---------------------------------------------------------------------------
+def pmc_run(args):
+    """A short run for one rocprofv3 counter pass: the tuned main step and a
+    plain device copy of COPY_BYTES."""
+    import torch
+    from paper_1010_4124_amd import lbm, tune
+    s = main_setup()
+    ctx = lbm.Context.from_setup(s)
+    f0 = ctx.init(*s.fields())
+    if args.variant is None:
+        tune.tune_context(ctx, f0, use_cache=False)
+    else:
+        ctx.variant = args.variant
+    log(f"pmc run: variant {ctx.variant} {lbm.lbm_step_variant_info(ctx.variant)}")
+    ctx.step(f0, args.steps, out=ctx.empty_f())
+    x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+
+
+def _rows(pattern):
+    import csv
+    rows = []
+    for p in glob.glob(pattern, recursive=True):
+        with open(p) as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def summarize(args):
+    """Markdown summary of the kernel-trace stats and the two counter passes."""
+    trace, fetch, write = args.summarize
+    stats = _rows(os.path.join(trace, "**", "*kernel_stats.csv"))
+    step = [r for r in stats if "k_step<" in r["Name"]]
+    if not step:
+        raise SystemExit(f"no step kernel in {trace}")
+    # the tuner launches every variant a few times; the timed one dominates
+    top = max(step, key=lambda r: int(r["Calls"]))
+    name = re.sub(r"^void ", "", top["Name"]).split("(")[0]
+    avg_ns = float(top["AverageNs"])
+
+    def per_dispatch(root, counter):
+        rows = _rows(os.path.join(root, "**", "*counter_collection.csv"))
+        by = {}
+        for r in rows:
+            if "k_step<" in r["Kernel_Name"] and r["Counter_Name"] == counter:
+                k = re.sub(r"^void ", "", r["Kernel_Name"]).split("(")[0]
+                by.setdefault(k, []).append(float(r["Counter_Value"]))
+        cp = [(int(r["Grid_Size"]), float(r["Counter_Value"])) for r in rows
+              if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == counter]
+        if not by or not cp:
+            raise SystemExit(f"{counter}: step or copy dispatches missing in {root}")
+        k = max(by, key=lambda q: len(by[q]))
+        if k != name:
+            raise SystemExit(f"{counter}: counted {k}, traced {name}")
+        return statistics.mean(by[k]), max(cp)[1]
+
+    f_k, f_c = per_dispatch(fetch, "FETCH_SIZE")
+    w_k, w_c = per_dispatch(write, "WRITE_SIZE")
+    sf, sw = COPY_BYTES / (f_c * 1024.0), COPY_BYTES / (w_c * 1024.0)
+    traffic = f_k * 1024.0 * sf + w_k * 1024.0 * sw
+    cells = 512 * 512
+    algo = BYTES_PER_LUP * cells
+    lines = [
+        "# Step kernel, 512 x 512 shear layer: duration and HBM traffic",
+        "",
+        f"kernel: {name}",
+        f"source_sha1: {source_hash()}",
+        f"avg_duration_ns: {avg_ns:.1f}",
+        f"calls: {top['Calls']}",
+        f"fetch_kib_per_dispatch: {f_k:.1f}",
+        f"write_kib_per_dispatch: {w_k:.1f}",
+        f"copy_fetch_kib: {f_c:.1f} (512 MiB copy; scale {sf:.4f})",
+        f"copy_write_kib: {w_c:.1f} (512 MiB copy; scale {sw:.4f})",
+        f"traffic_bytes_per_launch: {traffic:.6e}",
+        f"algorithmic_bytes_per_launch: {algo:.6e} (304 B x {cells} cells)",
+        f"traffic_per_lup: {traffic / cells:.1f} B (algorithmic 304 B)",
+        f"achieved_algorithmic_GBs: {algo / avg_ns:.1f}",
+        f"achieved_measured_GBs: {traffic / avg_ns:.1f}",
+        "",
+        "Commands (repository root, TMPDIR=/tmp):",
+    ]
+    lines += ["    " + c for c in args.commands] if args.commands else []
+    print("\n".join(lines))
+
+
+# ---------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--variant", type=int, default=None,
+                    help="step variant of the main workload (default: autotuned)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--large-steps", type=int, default=200)
+    ap.add_argument("--adj-steps", type=int, default=4000)
+    ap.add_argument("--adj-large-steps", type=int, default=200)
+    ap.add_argument("--batch-steps", type=int, default=10000)
+    ap.add_argument("--pmc-run", action="store_true")
+    ap.add_argument("--summarize", nargs=3, metavar=("TRACE", "FETCH", "WRITE"))
+    ap.add_argument("--commands", nargs="*")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the step is designed to shard by row slabs, see the design notes)", file=sys.stderr)
+        print(f"bench.py: one GPU only; --gpus {args.gpus} is not supported. The step shards by "
+              "row slabs with a 3-row halo exchange; that path is designed, not built.",
+              file=sys.stderr)
         sys.exit(2)
+    if args.summarize:
+        summarize(args)
+        return
 
     import torch
-
-    from paper_1010_4124_amd import inputs, lbm
     torch.cuda.set_device(0)
+    if args.pmc_run:
+        pmc_run(args)
+        return
 
-    setup = inputs.khi(512, 512, dx=1e-3, dy=1e-3, dt=1e-5, tau=1e-5, Dv=0.02, Drho=0.02)
-    ctx = lbm.Context.from_setup(setup)
-    f0 = ctx.init(*setup.fields())
-    log(f"forward 512^2: warmup {args.warmup}, timed {args.steps} steps, variant "
-        f"{lbm.lbm_step_variant_info(ctx.variant)}")
-    secs, f_end = time_forward(ctx, f0, args.steps, args.warmup)
-    lups = setup.nx * setup.ny * args.steps
+    s, ctx, f0, secs, wall, avg = bench_forward_main(args)
+    lups = s.nx * s.ny * args.steps
     mlups = lups / secs / 1e6
-    ms_step = secs / args.steps * 1e3
-    achieved = BYTES_PER_LUP * lups / secs / 1e9
-    log(f"forward 512^2: {mlups:.1f} MLUPS, {ms_step * 1e3:.2f} us/step")
-    rho = ctx.moments(f_end)[0]
-    if not torch.isfinite(rho).all():
-        raise SystemExit("non-finite state after the timed run")
-
-    extra = {}
-    # the 2048^2 shear layer: HBM-resident working set (2 x 637 MB)
-    big = inputs.khi(2048, 2048, dx=1e-3, dy=1e-3, dt=1e-5, tau=1e-5, Dv=0.01, Drho=0.04)
-    bctx = lbm.Context.from_setup(big)
-    bf0 = bctx.init(*big.fields())
-    bsecs, _ = time_forward(bctx, bf0, args.large_steps, 10)
-    blups = big.nx * big.ny * args.large_steps
-    extra["forward_2048"] = {
-        "MLUPS": blups / bsecs / 1e6, "steps": args.large_steps,
-        "us_per_step": bsecs / args.large_steps * 1e6,
-        "hbm_frac": BYTES_PER_LUP * blups / bsecs / 1e9 / HBM_PEAK_GBS,
-    }
-    log(f"forward 2048^2: {extra['forward_2048']}")
-    del bctx, bf0
+    kname = step_kernel_name(ctx.variant)
+    algo = BYTES_PER_LUP * s.nx * s.ny
+    achieved = algo / avg / 1e9
+    traffic = read_traffic(kname)
+    del ctx, f0
     torch.cuda.empty_cache()
 
+    extra = {}
+    if not args.no_extra:
+        extra["forward_2048"] = bench_forward_large(args)
+        extra["batched_sweep"] = bench_batch(args)
+        extra["adjoint"] = bench_adjoint(args)
+
     out = {
-        "metric": "MLUPS (D2V19+WENO5, FP64) fwd/adjoint/batched + % HBM roofline",
+        "metric": METRIC,
         "value": mlups,
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": secs / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "single shear layer (KHI) 512x512, periodic x, reflecting y, "
-                               "dx=dy=1e-3, dt=tau=1e-5, D_v=D_rho=0.02, forward step",
-                   "nx": 512, "ny": 512, "steps": args.steps},
+        "config": {"workload": "single shear layer (KHI) 512x512, periodic x, reflecting walls "
+                               "in y, dx=dy=1e-3, dt=tau=1e-5, D_v=D_rho=0.02, forward step",
+                   "nx": 512, "ny": 512, "steps": args.steps, "wall_s": wall},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": kname, "avg_launch_us": avg * 1e6,
+                     "algorithmic_bytes_per_launch": algo},
         "extra": extra,
     }
     if not args.no_cpu:
         log("cpu baseline ...")
-        small = inputs.khi(512, 512, dx=1e-3, dy=1e-3, dt=1e-5, tau=1e-5, Dv=0.02, Drho=0.02)
-        out["cpu_baseline"] = cpu_baseline(small, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(main_setup(), args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

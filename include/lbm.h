@@ -142,13 +142,23 @@ int lbm_sep_project(lbm_ctx* ctx, const double* g, const double* A, int32_t M, c
  * 64 x R cells and one of G groups of the 18 moving velocities; W is the
  * wavefronts-per-SIMD target that bounds the register budget; D planes are
  * prefetched ahead of the one being computed; NT = 1 stores f^{n+1} with
- * non-temporal stores. Every variant computes the same result; they differ in
- * speed only. lbm_set_step_variant selects the variant that later lbm_step
+ * non-temporal stores. Every variant evaluates the same formulas; results
+ * agree to rounding (the WENO face arithmetic is grouped per strip of R
+ * cells), and a given variant is deterministic. lbm_set_step_variant selects the variant that later lbm_step
  * calls of that context launch. */
 int lbm_step_variant_count(void);
 int lbm_step_variant_info(int32_t variant, int32_t* info5);
 int lbm_set_step_variant(lbm_ctx* ctx, int32_t variant);
 int lbm_get_step_variant(lbm_ctx* ctx, int32_t* variant);
+
+/* Autotuner. Times the step variants variants[0..nv) (nv = 0: all of them)
+ * on this context's grid: 2 warm-up steps, then nsteps >= 1 timed steps of
+ * lbm_step from f_in into f_tmp (f_in is not modified), bracketed by HIP
+ * events on `stream`. ms_out: NULL or host double[nv or count] receiving
+ * milliseconds per step. Leaves the fastest variant selected. Synchronous
+ * (waits for the timed work); on error the previous variant is kept. */
+int lbm_tune_step(lbm_ctx* ctx, const double* f_in, double* f_tmp, int32_t nsteps,
+                  const int32_t* variants, int32_t nv, double* ms_out, lbm_stream stream);
 
 /* ---- Batches of independent grids -------------------------------------
  *
@@ -216,6 +226,15 @@ int lbm_batch_get_step_variant(lbm_batch* b, int32_t* variant);
  * graph replays of C steps. out2 = (slots_per_xcd, graph_chunk). */
 int lbm_batch_set_schedule(lbm_batch* b, int32_t slots_per_xcd, int32_t graph_chunk);
 int lbm_batch_get_schedule(lbm_batch* b, int32_t* out2);
+
+/* Autotuner of a batch: times every (variant, slots_per_xcd) pair of
+ * variants[0..nv) x slots[0..ns) (nv = 0: all variants; ns = 0: the current
+ * slot count) like lbm_tune_step, without graphs; ms_out: NULL or host
+ * double[nv * ns] (row = variant). Leaves the fastest pair selected and the
+ * graph chunk unchanged. Synchronous. */
+int lbm_batch_tune(lbm_batch* b, const double* f_in, double* f_tmp, int32_t nsteps,
+                   const int32_t* variants, int32_t nv, const int32_t* slots, int32_t ns,
+                   double* ms_out, lbm_stream stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* lbm_last_error(void);

@@ -317,3 +317,49 @@ int lbm_sep_project(lbm_ctx* c, const double* g, const double* A, int32_t M, con
     hipError_t e = launch_sep_project(g, A, B, p.nx, p.ny, M, c->colbuf, out, (hipStream_t)stream);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_sep_project");
 }
+
+// Autotuner: time each listed variant on this grid with HIP events on
+// `stream` (warm-up steps first), keep the fastest.
+int lbm_tune_step(lbm_ctx* c, const double* f_in, double* f_tmp, int32_t nsteps,
+                  const int32_t* variants, int32_t nv, double* ms_out, lbm_stream stream)
+{
+    if (!c || !f_in || !f_tmp || nsteps < 1 || nv < 0 || (nv > 0 && !variants))
+        return fail(LBM_EINVAL, "bad argument%s%lld");
+    const int count = nv > 0 ? nv : step_variant_count();
+    for (int j = 0; j < count; ++j) {
+        const int v = nv > 0 ? variants[j] : j;
+        if (v < 0 || v >= step_variant_count()) return fail(LBM_EINVAL, "bad variant%s%lld");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return hip_fail(e, "lbm_tune_step");
+    }
+    const int keep = c->variant;
+    int best = keep, rc = LBM_OK;
+    double best_ms = 0.0;
+    for (int j = 0; j < count && rc == LBM_OK; ++j) {
+        c->variant = nv > 0 ? variants[j] : j;
+        float ms = 0.f;
+        if ((rc = lbm_step(c, f_in, f_tmp, 2, nullptr, stream)) != LBM_OK) break;
+        if ((e = hipEventRecord(e0, st)) != hipSuccess) { rc = hip_fail(e, "tune"); break; }
+        if ((rc = lbm_step(c, f_in, f_tmp, nsteps, nullptr, stream)) != LBM_OK) break;
+        if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+            (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+            rc = hip_fail(e, "tune");
+            break;
+        }
+        const double per = ms / nsteps;
+        if (ms_out) ms_out[j] = per;
+        if (j == 0 || per < best_ms) {
+            best_ms = per;
+            best = c->variant;
+        }
+    }
+    c->variant = rc == LBM_OK ? best : keep;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return rc;
+}

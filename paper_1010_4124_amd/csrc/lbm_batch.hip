@@ -555,3 +555,64 @@ int lbm_batch_get_schedule(lbm_batch* b, int32_t* out2)
 }
 
 }  // extern "C"
+
+extern "C" int lbm_batch_tune(lbm_batch* b, const double* f_in, double* f_tmp, int32_t nsteps,
+                              const int32_t* variants, int32_t nv, const int32_t* slots,
+                              int32_t ns, double* ms_out, lbm_stream stream)
+{
+    if (!b || !f_in || !f_tmp || nsteps < 1 || nv < 0 || ns < 0 || (nv > 0 && !variants) ||
+        (ns > 0 && !slots))
+        return bfail(LBM_EINVAL, "bad argument");
+    const int cv = nv > 0 ? nv : step_variant_count();
+    const int cs = ns > 0 ? ns : 1;
+    for (int j = 0; j < cv; ++j) {
+        const int v = nv > 0 ? variants[j] : j;
+        if (v < 0 || v >= step_variant_count()) return bfail(LBM_EINVAL, "bad variant");
+    }
+    for (int q = 0; q < cs; ++q)
+        if (ns > 0 && slots[q] < 0) return bfail(LBM_EINVAL, "bad slot count");
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return bhip(e, "lbm_batch_tune");
+    }
+    const int keep_v = b->variant, keep_s = b->slots, keep_c = b->graph_chunk;
+    int best_v = keep_v, best_s = keep_s, rc = LBM_OK;
+    double best_ms = 0.0;
+    b->graph_chunk = 0;
+    for (int j = 0; j < cv && rc == LBM_OK; ++j) {
+        if ((rc = lbm_batch_set_step_variant(b, nv > 0 ? variants[j] : j)) != LBM_OK) break;
+        for (int q = 0; q < cs && rc == LBM_OK; ++q) {
+            b->slots = ns > 0 ? slots[q] : keep_s;
+            float ms = 0.f;
+            if ((rc = lbm_batch_step(b, f_in, f_tmp, 2, nullptr, stream)) != LBM_OK) break;
+            if ((e = hipEventRecord(e0, st)) != hipSuccess) { rc = bhip(e, "tune"); break; }
+            if ((rc = lbm_batch_step(b, f_in, f_tmp, nsteps, nullptr, stream)) != LBM_OK) break;
+            if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+                (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+                rc = bhip(e, "tune");
+                break;
+            }
+            const double per = ms / nsteps;
+            if (ms_out) ms_out[j * cs + q] = per;
+            if ((j == 0 && q == 0) || per < best_ms) {
+                best_ms = per;
+                best_v = b->variant;
+                best_s = b->slots;
+            }
+        }
+    }
+    b->graph_chunk = keep_c;
+    if (rc == LBM_OK) {
+        rc = lbm_batch_set_step_variant(b, best_v);
+        b->slots = best_s;
+    } else {
+        lbm_batch_set_step_variant(b, keep_v);
+        b->slots = keep_s;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return rc;
+}

@@ -104,6 +104,9 @@ def lib():
         "lbm_batch_get_step_variant": (C.c_int, [_P, C.POINTER(_I)]),
         "lbm_batch_set_schedule": (C.c_int, [_P, _I, _I]),
         "lbm_batch_get_schedule": (C.c_int, [_P, C.POINTER(_I)]),
+        "lbm_tune_step": (C.c_int, [_P, _P, _P, _I, C.POINTER(_I), _I, C.POINTER(C.c_double), _P]),
+        "lbm_batch_tune": (C.c_int, [_P, _P, _P, _I, C.POINTER(_I), _I, C.POINTER(_I), _I,
+                                     C.POINTER(C.c_double), _P]),
         "lbm_last_error": (C.c_char_p, []),
         "lbm_version": (C.c_char_p, []),
     }
@@ -225,6 +228,17 @@ def lbm_get_step_variant(h):
     return v.value
 
 
+def lbm_tune_step(h, nx, ny, f_in, f_tmp, nsteps=20, variants=None, stream=None):
+    """Times the variants on this grid; returns {variant: ms per step} and
+    leaves the fastest selected."""
+    vs = list(range(lbm_step_variant_count())) if variants is None else [int(v) for v in variants]
+    ms = (C.c_double * len(vs))()
+    s = (NV, ny, nx)
+    _check(lib().lbm_tune_step(h, _ptr(f_in, s, "f_in"), _ptr(f_tmp, s, "f_tmp"), int(nsteps),
+                               (_I * len(vs))(*vs), len(vs), ms, _stream(stream)))
+    return {v: ms[j] for j, v in enumerate(vs)}
+
+
 # --- batches -------------------------------------------------------------------
 def lbm_batch_create(params, f_offset=None):
     """params: sequence of LbmParams; f_offset: None or int sequence."""
@@ -295,6 +309,20 @@ def lbm_batch_get_schedule(h):
     out = (_I * 2)()
     _check(lib().lbm_batch_get_schedule(h, out))
     return int(out[0]), int(out[1])
+
+
+def lbm_batch_tune(h, f_in, f_tmp, nsteps=10, variants=None, slots=None, stream=None):
+    """Times (variant, slots) pairs; returns {(variant, slots): ms per step}
+    and leaves the fastest selected."""
+    _, ext, _, _ = lbm_batch_info(h)
+    vs = list(range(lbm_step_variant_count())) if variants is None else [int(v) for v in variants]
+    cur = lbm_batch_get_schedule(h)[0]
+    ss = [cur] if slots is None else [int(x) for x in slots]
+    ms = (C.c_double * (len(vs) * len(ss)))()
+    _check(lib().lbm_batch_tune(h, _flat(f_in, ext, "f_in"), _flat(f_tmp, ext, "f_tmp"),
+                                int(nsteps), (_I * len(vs))(*vs), len(vs), (_I * len(ss))(*ss),
+                                len(ss), ms, _stream(stream)))
+    return {(v, q): ms[j * len(ss) + k] for j, v in enumerate(vs) for k, q in enumerate(ss)}
 
 
 class Batch:

@@ -1,0 +1,100 @@
+"""The single shear-layer workload at full size and full length (512 x 512,
+20000 steps, the launch configuration the benchmark times) against the
+oracle's stored run (tests/golden/khi512_oracle.npz, written by
+tests/golden/make_khi512_golden.py from oracle/ alone).
+
+Compared: f at 4096 seeded samples and the moments at 1024 seeded cells
+after 1000, 5000 and 20000 steps (normwise against max |f|), the energy log
+every 100 steps, and the conserved totals.
+
+Tolerance. Both sides evaluate the same formulas in a different order (the
+oracle: f^eq with divisions, unfused sums, the BGK term as written; the
+kernel: division-free regrouped WENO weights and equilibrium, fused
+multiply-adds, (1 - dt/tau) f + (dt/tau) f^eq). One step differs by a few
+units in the last place of f, about 3e-16 max|f|, and the difference is
+carried forward. The bar is the 1e-12 normwise parity up to 1000 steps and
+DRIFT * n beyond (DRIFT = 3.5e-16 per step, above the measured 2-3e-16)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1010_4124_amd import inputs, lbm
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "khi512_oracle.npz")
+TOL = 1e-12
+DRIFT = 3.5e-16
+
+
+def tol(n):
+    return max(TOL, DRIFT * n)
+
+
+@pytest.fixture(scope="module")
+def gold():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    torch.cuda.set_device(0)
+    return np.load(GOLD)
+
+
+def test_khi512_full_run_matches_oracle(gold):
+    s = inputs.khi(512, 512, dx=1e-3, dy=1e-3, dt=1e-5, tau=1e-5, Dv=0.02, Drho=0.02)
+    ctx = lbm.Context.from_setup(s)
+    f = ctx.init(*s.fields())
+    every = int(gold["ke_every"])
+    checks = [int(c) for c in gold["checkpoints"]]
+    ke = []
+    n = 0
+    vx = torch.tensor([0.0] + [v * c for v in (1.0, 2.0, 3.0)
+                               for c in (0.5, -0.5, -1.0, -0.5, 0.5, 1.0)],
+                      dtype=torch.float64, device=f.device)
+    hv2 = torch.tensor([0.0] + [0.5 * v * v for v in (1.0, 2.0, 3.0) for _ in range(6)],
+                       dtype=torch.float64, device=f.device)
+    worst = {}
+    out = ctx.empty_f()
+    while n < 20000:
+        f_next, log = ctx.step(f, every, out=out, ke_log=True)
+        ke.append(log.cpu().numpy())
+        out, f = f, f_next
+        n += every
+        if n in checks:
+            fmax = float(gold[f"fmax_{n}"])
+            got = f[torch.as_tensor(gold["sample_i"]), torch.as_tensor(gold["sample_y"]),
+                    torch.as_tensor(gold["sample_x"])].cpu().numpy()
+            err_f = float(np.abs(got - gold[f"f_{n}"]).max() / fmax)
+            mom = [m.cpu().numpy()[gold["cell_y"], gold["cell_x"]] for m in ctx.moments(f)]
+            ref_m = gold[f"mom_{n}"]
+            # velocities against the velocity scale max|u| (u_y alone is a
+            # small difference of O(1) sums), rho and T against their own
+            vscale = max(np.abs(ref_m[1]).max(), np.abs(ref_m[2]).max())
+            scales = (np.abs(ref_m[0]).max(), vscale, vscale, np.abs(ref_m[3]).max())
+            err_m = max(float(np.abs(g - e).max() / sc) for g, e, sc in zip(mom, ref_m, scales))
+            tot = np.array([float(f.sum()), float((vx[:, None, None] * f).sum()),
+                            float((hv2[:, None, None] * f).sum())])
+            ref = gold[f"totals_{n}"]
+            err_tot = (abs(tot[0] - ref[0]) / abs(ref[0]),
+                       abs(tot[1] - ref[1]) / abs(ref[0]),  # x-momentum: scale by mass
+                       abs(tot[2] - ref[2]) / abs(ref[2]))
+            worst[n] = (err_f, err_m) + err_tot
+            print(f"step {n}: f {err_f:.2e}, moments {err_m:.2e}, mass {err_tot[0]:.1e}, "
+                  f"px {err_tot[1]:.1e}, energy {err_tot[2]:.1e}", flush=True)
+    ke = np.concatenate(ke)  # ke[n] = state at step n, n < 20000
+    ref = gold["ke"]  # every 100 steps, 0..20000
+    got = np.concatenate([ke[::every], ctx.kinetic_y(f).cpu().numpy()[None]])
+    # E_y is a small difference-dominated quantity (u_y ~ 1e-3): judge its
+    # error against the flow's kinetic energy sum rho |u|^2 / 2 dx dy
+    r0, ux0, uy0, _ = s.fields()
+    e_kin = float((0.5 * r0 * (ux0 ** 2 + uy0 ** 2)).sum()) * s.dx * s.dy
+    steps = np.arange(got.shape[0]) * every
+    for c, scale in ((0, e_kin), (1, float((0.5 * r0 * (ux0 ** 2 + uy0 ** 2)).max()))):
+        d = np.abs(got[:, c] - ref[:, c]) / scale
+        rel = np.abs(got[:, c] - ref[:, c]) / np.abs(ref[:, c])
+        print(f"energy log column {c}: worst error {d.max():.2e} of the kinetic energy scale, "
+              f"{rel.max():.2e} relative to E_y itself", flush=True)
+        assert np.all(d <= np.maximum(TOL, DRIFT * steps)), c
+    for n, (ef, em, m, px, en) in worst.items():
+        assert ef < tol(n) and em < tol(n), (n, ef, em)
+        assert max(m, px, en) < max(1e-13, 1.5e-16 * n), (n, m, px, en)
