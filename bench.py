@@ -101,8 +101,9 @@ def read_traffic(kernel_name):
 
 def step_kernel_name(variant):
     from paper_1010_4124_amd import lbm
-    R, G, W, D, NT = lbm.lbm_step_variant_info(variant)
-    return f"lbmd::k_step<{R}, {G}, {W}, {D}, {'true' if NT else 'false'}>"
+    R, G, W, D, NT, M = lbm.lbm_step_variant_info(variant)
+    b = lambda x: "true" if x else "false"
+    return f"lbmd::k_step<{R}, {G}, {W}, {D}, {b(NT)}, {b(M)}>"
 
 
 # ---------------------------------------------------------------------------

@@ -122,7 +122,8 @@ int lbm_create(const lbm_params* p, lbm_ctx** out)
     if (2 * c->ke_cap < 4 * NV) c->ke_cap = 2 * NV;
     if ((e = hipMalloc(&c->scratch, NV * n * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&c->ke_part, 2 * (size_t)c->ke_cap * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&c->colbuf, (size_t)p->nx * sizeof(double))) != hipSuccess) {
+        (e = hipMalloc(&c->colbuf, (size_t)p->nx * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&c->msum, 8 * n * sizeof(double))) != hipSuccess) {
         lbm_destroy(c);
         g_err = std::string("hipMalloc: ") + hipGetErrorString(e);
         return LBM_ENOMEM;
@@ -147,6 +148,7 @@ void lbm_destroy(lbm_ctx* c)
     if (c->scratch) hipFree(c->scratch);
     if (c->ke_part) hipFree(c->ke_part);
     if (c->colbuf) hipFree(c->colbuf);
+    if (c->msum) hipFree(c->msum);
     delete c;
 }
 
@@ -185,12 +187,22 @@ int lbm_step(lbm_ctx* c, const double* f_in, double* f_out, int32_t nsteps, doub
     const lbm_params& p = c->p;
     const double cx = p.dt / p.dx, cy = p.dt / p.dy, ct = p.dt / p.tau;
     const int ntiles = step_ntiles(c->variant, p.nx, p.ny);
+    int info[6];
+    step_variant_desc(c->variant, info);
+    const bool carried = info[5] != 0;
+    if (carried) {
+        // moment sums of f_in; each step then reads one set and writes the other
+        hipError_t e = launch_sums(f_in, c->msum, c->k, n, st);
+        if (e != hipSuccess) return hip_fail(e, "lbm_step sums");
+    }
     for (int s = 0; s < nsteps; ++s) {
         // step s writes f_out when (nsteps - 1 - s) is even, else the scratch
         const double* src = s == 0 ? f_in : (((nsteps - s) % 2 == 0) ? f_out : c->scratch);
         double* dst = ((nsteps - 1 - s) % 2 == 0) ? f_out : c->scratch;
+        const double* m_in = carried ? c->msum + 4 * n * (s % 2) : nullptr;
+        double* m_out = carried ? c->msum + 4 * n * ((s + 1) % 2) : nullptr;
         hipError_t e = launch_step(c->variant, src, dst, c->k, ke_log ? c->ke_part : nullptr,
-                                   p.nx, p.ny, p.bc, cx, cy, ct, st);
+                                   p.nx, p.ny, p.bc, cx, cy, ct, m_in, m_out, st);
         if (e != hipSuccess) return hip_fail(e, "lbm_step");
         if (ke_log) {
             e = launch_reduce_pairs(c->ke_part, ntiles, p.dx * p.dy, ke_log + 2 * s, st);
@@ -226,16 +238,11 @@ int lbm_kinetic_y(lbm_ctx* c, const double* f, double* out2, lbm_stream stream)
 
 int lbm_step_variant_count(void) { return step_variant_count(); }
 
-int lbm_step_variant_info(int32_t v, int32_t* info5)
+int lbm_step_variant_info(int32_t v, int32_t* info6)
 {
-    int R = 0, G = 0, W = 0, D = 0, NT = 0;
-    if (!info5 || step_variant_desc(v, &R, &G, &W, &D, &NT))
-        return fail(LBM_EINVAL, "bad variant%s%lld");
-    info5[0] = R;
-    info5[1] = G;
-    info5[2] = W;
-    info5[3] = D;
-    info5[4] = NT;
+    int d[6];
+    if (!info6 || step_variant_desc(v, d)) return fail(LBM_EINVAL, "bad variant%s%lld");
+    for (int j = 0; j < 6; ++j) info6[j] = d[j];
     return LBM_OK;
 }
 
@@ -254,21 +261,20 @@ int lbm_get_step_variant(lbm_ctx* c, int32_t* v)
 }
 
 // Default step variant (the autotuner can override it per context or batch):
-// on large grids (or batches) one velocity group with two planes in flight and non-temporal
-// stores; on small grids three velocity groups, so that there are enough
-// workgroups for all 256 CUs.
+// tiles of 64 x 4 cells, three waves per tile; on large grids (or batches)
+// the moment sums are carried from step to step.
 int lbmi_default_variant(int nx, int ny) { return lbmi_default_variant_cells((int64_t)nx * ny); }
 
 int lbmi_default_variant_cells(int64_t cells)
 {
-    const int want[5] = {4, cells >= (1ll << 21) ? 1 : 3, 3, cells >= (1ll << 21) ? 2 : 1,
-                         cells >= (1ll << 21) ? 1 : 0};
+    const bool large = cells >= (1ll << 21);
+    const int want[6] = {4, 3, 3, 1, 0, large ? 1 : 0};
     for (int v = 0; v < step_variant_count(); ++v) {
-        int d[5];
-        step_variant_desc(v, &d[0], &d[1], &d[2], &d[3], &d[4]);
-        if (d[0] == want[0] && d[1] == want[1] && d[2] == want[2] && d[3] == want[3] &&
-            d[4] == want[4])
-            return v;
+        int d[6];
+        step_variant_desc(v, d);
+        bool same = true;
+        for (int j = 0; j < 6; ++j) same = same && d[j] == want[j];
+        if (same) return v;
     }
     return 0;
 }

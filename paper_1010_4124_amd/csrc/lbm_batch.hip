@@ -2,9 +2,9 @@
 // sizes (one D2V19 FDLB step, Eq. (47) of arXiv:1010.4124, per grid per
 // launch) and the lbm_batch_* entry points of the C-ABI.
 //
-// The work items (instance, tile, velocity group) of all instances form one
-// flat list, instance-major. A launch has 8 * slots one-wavefront
-// workgroups; workgroup b runs on XCD b % 8 and walks the band of the list
+// The tiles of all instances form one flat work list, instance-major. A
+// launch has 8 * slots workgroups (G wavefronts each, as the step variant
+// says); workgroup b runs on XCD b % 8 and walks the band of the list
 // that belongs to that XCD with stride `slots`, so each XCD sweeps one
 // contiguous range of tiles (neighbouring tiles share halos in that XCD's
 // L2). With slots equal to the band length every workgroup takes exactly one
@@ -34,6 +34,7 @@ namespace lbmd {
 // Device-resident description of one instance.
 struct BatchInst {
     int64_t off;     // element offset of the instance's [19][ny][nx] block
+    int64_t moff;    // element offset of its [4][ny][nx] moment sums
     int nx, ny;
     int bc[4];
     int tiles_x;
@@ -49,16 +50,18 @@ struct BatchArgs {
     double* __restrict__ fout;
     double* __restrict__ ke_part;          // [sum of ntiles][2] or null
     const BatchInst* __restrict__ inst;
-    const int2* __restrict__ work;         // item -> (instance, tile * G + group)
+    const int2* __restrict__ work;         // item -> (instance, tile x groups or tile)
+    const double* __restrict__ m_in;       // carried moment sums (M variants)
+    double* __restrict__ m_out;
     int nwork, per_xcd, slots;
     Consts k;
 };
 
-template <int R, int G, int W, int DEPTH, bool NT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_step_batch(BatchArgs a)
+template <int R, int G, int W, int DEPTH, bool NT, bool CM>
+__global__ __launch_bounds__((64 * Waves<G, CM>::N)) __attribute__((amdgpu_waves_per_eu(W)))
+void k_step_batch(BatchArgs a)
 {
-    __shared__ double s_pl[Stage<R>::SLOTS];
-    __shared__ double s_dx[R * XPITCH];
+    __shared__ double lds[Waves<G, CM>::N * WaveLds<R>::SIZE];
 
     const int b = blockIdx.x;
     const int lo = (b & 7) * a.per_xcd;
@@ -79,10 +82,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_
         s.cx = d.cx;
         s.cy = d.cy;
         s.ct = d.ct;
-        const int tile = it.y / G, grp = it.y - tile * G;
-        step_work<R, G, DEPTH, NT>(s, a.k, SideEqPtr{d.side_eq}, tile, grp,
-                                   a.ke_part ? a.ke_part + 2 * ((int64_t)d.ke_off + tile) : nullptr,
-                                   s_pl, s_dx);
+        constexpr int GW = CM ? 1 : G;
+        const int tile = it.y / GW, grp = it.y - tile * GW;
+        step_work<R, G, DEPTH, NT, CM>(
+            s, a.k, SideEqPtr{d.side_eq}, tile, grp,
+            a.ke_part ? a.ke_part + 2 * ((int64_t)d.ke_off + tile) : nullptr, lds,
+            CM ? a.m_in + d.moff : nullptr, CM ? a.m_out + d.moff : nullptr);
         __syncthreads();  // LDS is reused by the next item
     }
 }
@@ -118,10 +123,10 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const double* __restrict__
 }
 
 struct BatchVariant {
-    int R, G;
+    int R, G, M;
     void (*kernel)(BatchArgs);
 };
-#define LBM_BATCH_VARIANT(R, G, W, D, NT) {R, G, k_step_batch<R, G, W, D, NT>},
+#define LBM_BATCH_VARIANT(R, G, W, D, NT, M) {R, G, M, k_step_batch<R, G, W, D, NT, M>},
 static const BatchVariant kBatchVariants[] = {LBM_STEP_VARIANTS(LBM_BATCH_VARIANT)};
 #undef LBM_BATCH_VARIANT
 
@@ -150,6 +155,7 @@ struct lbm_batch {
     double* scratch = nullptr;
     double* ke_part = nullptr;
     double* ke_ring = nullptr;  // [n][graph_chunk][2]
+    double* msum = nullptr;     // 2 x (4 * cells): carried moment sums, ping-pong
     int ring_cap = 0;
     hipStream_t cap = nullptr;  // private stream used only for capture
     struct Graph {
@@ -192,14 +198,14 @@ int build_tables(lbm_batch* b)
         d.ntiles = d.tiles_x * ((d.ny + V.R - 1) / V.R);
         d.ke_off = (int)ntiles;
         ntiles += d.ntiles;
-        nwork += (int64_t)d.ntiles * V.G;
+        nwork += (int64_t)d.ntiles * (V.M ? 1 : V.G);
     }
     if (nwork > b->work_cap || ntiles > b->ke_cap)
         return bfail(LBM_EINVAL, "batch work list exceeds its allocation");
     std::vector<int2> w((size_t)nwork);
     size_t q = 0;
     for (int i = 0; i < b->n; ++i)
-        for (int t = 0; t < b->hinst[i].ntiles * V.G; ++t) w[q++] = make_int2(i, t);
+        for (int t = 0; t < b->hinst[i].ntiles * (V.M ? 1 : V.G); ++t) w[q++] = make_int2(i, t);
     hipError_t e;
     if ((e = hipMemcpy(b->inst, b->hinst.data(), sizeof(BatchInst) * b->n,
                        hipMemcpyHostToDevice)) != hipSuccess ||
@@ -211,10 +217,14 @@ int build_tables(lbm_batch* b)
     return LBM_OK;
 }
 
-hipError_t launch_batch_step(lbm_batch* b, const double* src, double* dst, bool ke, hipStream_t st)
+// Step s of a call reads moment set s % 2 and writes the other one.
+hipError_t launch_batch_step(lbm_batch* b, const double* src, double* dst, bool ke, int parity,
+                             hipStream_t st)
 {
     const BatchVariant& V = kBatchVariants[b->variant];
     BatchArgs a;
+    a.m_in = V.M ? b->msum + 4 * b->cells * parity : nullptr;
+    a.m_out = V.M ? b->msum + 4 * b->cells * (1 - parity) : nullptr;
     a.fin = src;
     a.fout = dst;
     a.ke_part = ke ? b->ke_part : nullptr;
@@ -224,7 +234,7 @@ hipError_t launch_batch_step(lbm_batch* b, const double* src, double* dst, bool 
     a.per_xcd = (b->nwork + 7) / 8;
     a.slots = b->slots > 0 ? std::min(b->slots, a.per_xcd) : a.per_xcd;
     a.k = b->k;
-    hipLaunchKernelGGL(V.kernel, dim3(8 * a.slots), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(V.kernel, dim3(8 * a.slots), dim3(64 * (V.M ? V.G : 1)), 0, st, a);
     return hipGetLastError();
 }
 
@@ -272,7 +282,7 @@ int get_graph(lbm_batch* b, const double* x, double* y, bool ke, hipGraphExec_t*
     for (int s = 0; s < b->graph_chunk && le == hipSuccess; ++s) {
         const double* src = (s % 2 == 0) ? x : y;
         double* dst = (s % 2 == 0) ? y : (double*)x;
-        le = launch_batch_step(b, src, dst, ke, b->cap);
+        le = launch_batch_step(b, src, dst, ke, (1 + s) % 2, b->cap);
         if (le == hipSuccess && ke) le = launch_batch_reduce(b, b->ke_ring, 2 * b->graph_chunk, 2 * s, b->cap);
     }
     hipGraph_t graph = nullptr;
@@ -356,7 +366,7 @@ int lbm_batch_create(const lbm_params* inst, int32_t n, const int64_t* f_offset,
             const int64_t nt = (int64_t)((inst[i].nx + TX - 1) / TX) *
                                ((inst[i].ny + kBatchVariants[v].R - 1) / kBatchVariants[v].R);
             t += nt;
-            w += nt * kBatchVariants[v].G;
+            w += nt * (kBatchVariants[v].M ? 1 : kBatchVariants[v].G);
         }
         wmax = std::max(wmax, w);
         tmax = std::max(tmax, t);
@@ -372,6 +382,7 @@ int lbm_batch_create(const lbm_params* inst, int32_t n, const int64_t* f_offset,
         (e = hipMalloc(&b->ke_part, sizeof(double) * 2 * (size_t)b->ke_cap)) != hipSuccess ||
         (e = hipMalloc(&b->inst, sizeof(BatchInst) * (size_t)n)) != hipSuccess ||
         (e = hipMalloc(&b->work, sizeof(int2) * (size_t)b->work_cap)) != hipSuccess ||
+        (e = hipMalloc(&b->msum, sizeof(double) * 8 * (size_t)b->cells)) != hipSuccess ||
         (e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess) {
         lbm_batch_destroy(b);
         return bfail(LBM_ENOMEM, std::string("batch allocation: ") + hipGetErrorString(e));
@@ -381,6 +392,7 @@ int lbm_batch_create(const lbm_params* inst, int32_t n, const int64_t* f_offset,
         BatchInst& d = b->hinst[i];
         std::memset(&d, 0, sizeof(d));
         d.off = b->off[i];
+        d.moff = 4 * b->cell_off[i];
         d.nx = q.nx;
         d.ny = q.ny;
         for (int s = 0; s < 4; ++s) d.bc[s] = q.bc[s];
@@ -418,6 +430,7 @@ void lbm_batch_destroy(lbm_batch* b)
     if (b->ke_ring) hipFree(b->ke_ring);
     if (b->inst) hipFree(b->inst);
     if (b->work) hipFree(b->work);
+    if (b->msum) hipFree(b->msum);
     delete b;
 }
 
@@ -479,9 +492,17 @@ int lbm_batch_step(lbm_batch* b, const double* f_in, double* f_out, int32_t nste
     const bool ke = ke_log != nullptr;
     // step s writes f_out when (nsteps - 1 - s) is even, else the scratch
     auto dst_of = [&](int s) { return ((nsteps - 1 - s) % 2 == 0) ? f_out : b->scratch; };
+    if (kBatchVariants[b->variant].M) {
+        // moment sums of f_in for the first step (set 0)
+        for (int i = 0; i < b->n; ++i) {
+            hipError_t e = launch_sums(f_in + b->off[i], b->msum + 4 * b->cell_off[i], b->k,
+                                       (int64_t)b->p[i].nx * b->p[i].ny, st);
+            if (e != hipSuccess) return bhip(e, "lbm_batch_step sums");
+        }
+    }
     auto eager = [&](int s) -> int {
         const double* src = s == 0 ? f_in : dst_of(s - 1);
-        hipError_t e = launch_batch_step(b, src, dst_of(s), ke, st);
+        hipError_t e = launch_batch_step(b, src, dst_of(s), ke, s % 2, st);
         if (e == hipSuccess && ke) e = launch_batch_reduce(b, ke_log, 2 * (int64_t)nsteps, 2 * (int64_t)s, st);
         return e == hipSuccess ? LBM_OK : bhip(e, "lbm_batch_step");
     };

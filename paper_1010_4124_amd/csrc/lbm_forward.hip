@@ -2,12 +2,12 @@
 //
 // One launch of k_step advances every cell of one grid by one forward-Euler
 // step of the D2V19 FDLB model (Eq. (47) of arXiv:1010.4124); the tile body
-// is in lbm_step.h. Work items (tile, velocity group) map to one-wavefront
-// workgroups XCD-major: hardware dispatches consecutive workgroups
-// round-robin over the 8 XCDs, so workgroup b takes work item
-// (b % 8) * per_xcd + b / 8 and every XCD sweeps one contiguous band of tiles
-// whose halos then meet in that XCD's L2. The per-context constants travel by
-// value in the kernel arguments and are read with scalar loads.
+// is in lbm_step.h. Tiles map to workgroups (G wavefronts each) XCD-major:
+// hardware dispatches consecutive workgroups round-robin over the 8 XCDs, so
+// workgroup b takes tile (b % 8) * per_xcd + b / 8 and every XCD sweeps one
+// contiguous band of tiles whose halos then meet in that XCD's L2. The
+// per-context constants travel by value in the kernel arguments and are read
+// with scalar loads.
 //
 // The remaining kernels here are the cell-parallel helpers: f^eq
 // initialisation, side equilibria, moments and the kinetic-energy reduction.
@@ -21,22 +21,47 @@ namespace lbmd {
 struct StepArgs {
     StepGrid s;
     double* __restrict__ ke_part;  // [ntiles][2] or null
-    int nwork, per_xcd;
+    const double* __restrict__ m_in;  // carried moment sums [4][ny][nx] (M variants)
+    double* __restrict__ m_out;
+    int nwork, per_xcd;  // work items: tiles (M = 1) or tiles x groups (M = 0)
     Consts k;
 };
 
-template <int R, int G, int W, int DEPTH, bool NT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_step(StepArgs a)
+template <int R, int G, int W, int DEPTH, bool NT, bool CM>
+__global__ __launch_bounds__((64 * Waves<G, CM>::N)) __attribute__((amdgpu_waves_per_eu(W)))
+void k_step(StepArgs a)
 {
-    __shared__ double s_pl[Stage<R>::SLOTS];
-    __shared__ double s_dx[R * XPITCH];
+    __shared__ double lds[Waves<G, CM>::N * WaveLds<R>::SIZE];
 
     const int b = blockIdx.x;
     const int work = (b & 7) * a.per_xcd + (b >> 3);
     if (work >= a.nwork) return;
-    const int tile = work / G, grp = work - tile * G;
-    step_work<R, G, DEPTH, NT>(a.s, a.k, SideEqConsts{}, tile, grp,
-                               a.ke_part ? a.ke_part + 2 * tile : nullptr, s_pl, s_dx);
+    constexpr int GW = CM ? 1 : G;  // groups per work item's tile index
+    const int tile = work / GW, grp = work - tile * GW;
+    step_work<R, G, DEPTH, NT, CM>(a.s, a.k, SideEqConsts{}, tile, grp,
+                                   a.ke_part ? a.ke_part + 2 * tile : nullptr, lds, a.m_in,
+                                   a.m_out);
+}
+
+// Moment sums rho, j_x, j_y, E (Eq. (10)) per cell, in the order the step
+// kernels accumulate them: the state a carried-moment step starts from.
+__global__ void k_sums(const double* __restrict__ f, double* __restrict__ m, int64_t n, Consts k)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const double fi = f[i * n + c];
+        r += fi;
+        jx = __builtin_fma(fi, k.vx[i], jx);
+        jy = __builtin_fma(fi, k.vy[i], jy);
+        E = __builtin_fma(fi, k.hv2[i], E);
+    }
+    m[c] = r;
+    m[n + c] = jx;
+    m[2 * n + c] = jy;
+    m[3 * n + c] = E;
 }
 
 // ---------------------------------------------------------------------------
@@ -168,24 +193,26 @@ __global__ __launch_bounds__(256) void k_reduce_pairs(const double* __restrict__
 
 // ---------------------------------------------------------------------------
 struct StepVariant {
-    int R, G, W, D, NT;
+    int R, G, W, D, NT, M;
     void (*kernel)(StepArgs);
 };
 
-#define LBM_SINGLE_VARIANT(R, G, W, D, NT) {R, G, W, D, NT, k_step<R, G, W, D, NT>},
+#define LBM_SINGLE_VARIANT(R, G, W, D, NT, M) {R, G, W, D, NT, M, k_step<R, G, W, D, NT, M>},
 static const StepVariant kStepVariants[] = {LBM_STEP_VARIANTS(LBM_SINGLE_VARIANT)};
 #undef LBM_SINGLE_VARIANT
 constexpr int kNumStepVariants = sizeof(kStepVariants) / sizeof(kStepVariants[0]);
 
 int step_variant_count() { return kNumStepVariants; }
-int step_variant_desc(int v, int* R, int* G, int* W, int* D, int* NT)
+int step_variant_desc(int v, int info[6])
 {
     if (v < 0 || v >= kNumStepVariants) return -1;
-    *R = kStepVariants[v].R;
-    *G = kStepVariants[v].G;
-    *W = kStepVariants[v].W;
-    *D = kStepVariants[v].D;
-    *NT = kStepVariants[v].NT;
+    const StepVariant& V = kStepVariants[v];
+    info[0] = V.R;
+    info[1] = V.G;
+    info[2] = V.W;
+    info[3] = V.D;
+    info[4] = V.NT;
+    info[5] = V.M;
     return 0;
 }
 
@@ -197,7 +224,7 @@ int step_ntiles(int variant, int nx, int ny)
 
 hipError_t launch_step(int variant, const double* fin, double* fout, const Consts& k,
                        double* ke_part, int nx, int ny, const int bc[4], double cx, double cy,
-                       double ct, hipStream_t st)
+                       double ct, const double* m_in, double* m_out, hipStream_t st)
 {
     const StepVariant& V = kStepVariants[variant];
     StepArgs a;
@@ -211,10 +238,19 @@ hipError_t launch_step(int variant, const double* fin, double* fout, const Const
     a.s.cy = cy;
     a.s.ct = ct;
     a.ke_part = ke_part;
-    a.nwork = a.s.tiles_x * ((ny + V.R - 1) / V.R) * V.G;
+    a.m_in = m_in;
+    a.m_out = m_out;
+    a.nwork = a.s.tiles_x * ((ny + V.R - 1) / V.R) * (V.M ? 1 : V.G);
     a.per_xcd = (a.nwork + 7) / 8;
     a.k = k;
-    hipLaunchKernelGGL(V.kernel, dim3(8 * a.per_xcd), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(V.kernel, dim3(8 * a.per_xcd), dim3(64 * (V.M ? V.G : 1)), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sums(const double* f, double* m, const Consts& k, int64_t n, hipStream_t st)
+{
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_sums, dim3((unsigned)blocks), dim3(256), 0, st, f, m, n, k);
     return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@ struct lbm_ctx {
     double* scratch = nullptr;     // 19 planes: ping-pong state of multi-step calls
     double* ke_part = nullptr;     // [ke_cap][2] diagnostic partials
     double* colbuf = nullptr;      // nx doubles: column sums of lbm_sep_project
+    double* msum = nullptr;        // 2 x [4][ny][nx]: carried moment sums (ping-pong)
 };
 
 int lbmi_validate(const lbm_params* p);
@@ -27,11 +28,12 @@ void lbmi_set_error(const char* msg);
 
 namespace lbmd {
 int step_variant_count();
-int step_variant_desc(int v, int* R, int* G, int* W, int* D, int* NT);
+int step_variant_desc(int v, int info[6]);
 int step_ntiles(int variant, int nx, int ny);
 hipError_t launch_step(int variant, const double* fin, double* fout, const Consts& k,
                        double* ke_part, int nx, int ny, const int bc[4], double cx, double cy,
-                       double ct, hipStream_t st);
+                       double ct, const double* m_in, double* m_out, hipStream_t st);
+hipError_t launch_sums(const double* f, double* m, const Consts& k, int64_t n, hipStream_t st);
 hipError_t launch_reduce_pairs(const double* part, int n, double dxdy, double* out2,
                                hipStream_t st);
 hipError_t launch_init(const double* rho, const double* ux, const double* uy, const double* T,

@@ -2,14 +2,19 @@
 // arXiv:1010.4124) for one 64 x R tile, shared by the single-grid kernel
 // (lbm_forward.hip) and the batched kernel (lbm_batch.hip).
 //
-// A work item is one tile and one of G groups of the 18 moving velocities;
-// each lane owns a column strip of R cells.
+// The 18 moving velocities are split into G groups. Without carried moments
+// (M = 0) each group of a tile is a separate one-wavefront workgroup that
+// forms the tile's moments itself; with carried moments (M = 1) the G groups
+// are the wavefronts of one workgroup, each with its own LDS region. Each
+// lane owns a column strip of R cells.
 //
-//   phase 1  every lane loads the 19 values of its R cells, forms the moments
-//            of Eq. (10) and keeps u/T, 1-u^2/2T and rho F_k(T) in
-//            registers. Group 0 also relaxes and stores the rest particle and
-//            reduces the tile's transverse kinetic energy.
-//   phase 2  for each velocity i of the group:
+//   phase 1  the moments of Eq. (10) of the tile's cells: summed over the 19
+//            planes (M = 0), or read back from the sums rho, j, E that the
+//            previous step wrote (M = 1). Every lane keeps u/T, 1-u^2/2T and
+//            rho, T of its cells in registers. Group 0 also relaxes and
+//            stores the rest particle and reduces the tile's transverse
+//            kinetic energy.
+//   phase 2  for each velocity i of the wave's group:
 //            - plane f_i of the tile plus a 3-cell cross-shaped halo (ghosts
 //              from the boundary rule) is staged in LDS; the next plane is
 //              already in flight into registers (software pipeline);
@@ -20,9 +25,9 @@
 //              strip in registers;
 //            - each lane combines convection, BGK relaxation toward f^eq and
 //              the Euler update and stores f_i^{n+1} (coalesced along x).
-//
-// A tile's G work items repeat phase 1 (the 19 centre values come from L2);
-// G > 1 multiplies the number of workgroups on small grids.
+//   phase 3  (carried moments) the waves' partial sums of rho, j, E over the
+//            f^{n+1} values they stored are added up in a fixed order and
+//            written for the next step.
 #pragma once
 
 #include "lbm_device.h"
@@ -94,26 +99,71 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// Phase 2 of one tile: this group's moving velocities. Instantiated once for
+// Per-wave LDS region: the staged plane, the x flux differences, and (reused)
+// the exchange of the 4 x R moment sums of the wave's lanes.
+template <int R>
+struct WaveLds {
+    static constexpr int DX = Stage<R>::SLOTS;
+    static constexpr int WORK = Stage<R>::SLOTS + R * XPITCH;
+    static constexpr int XCH = 4 * R * 64;
+    static constexpr int SIZE = WORK > XCH ? WORK : XCH;
+};
+
+// Waves per workgroup of a variant: the G groups are waves of one workgroup
+// only with carried moments.
+template <int G, bool CM>
+struct Waves {
+    static constexpr int N = CM ? G : 1;
+};
+
+// Orders one wave's LDS accesses between the staging, x-pass and y-pass of a
+// plane. A one-wave workgroup uses the workgroup barrier; in a multi-wave
+// workgroup each wave works in its own LDS region, LDS operations of a wave
+// execute in issue order, and a wave-scope fence keeps the compiler from
+// moving them across.
+template <int G>
+__device__ __forceinline__ void plane_sync()
+{
+    if constexpr (G == 1) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// Sums rho, j_x, j_y, E of R cells (the four moment sums of Eq. (10)).
+template <int R>
+struct Sums {
+    double r[R], jx[R], jy[R], E[R];
+};
+
+// Phase 2 of one tile: this wave's moving velocities. Instantiated once for
 // interior tiles and once for boundary tiles, so that each loop is straight
 // line code and the compiler tracks its outstanding loads and stores exactly.
 // DEPTH planes are in flight ahead of the one being computed; every load is
 // issued unconditionally (past the group's last plane the last plane is
 // re-read) and consumed after the current plane's stores, so waiting for a
-// staged plane never waits for stores.
-template <int R, int G, bool BND, int DEPTH, bool NT, class SE>
+// staged plane never waits for stores. With CM the sums of the new values
+// are accumulated into `acc`.
+template <int R, int G, bool BND, int DEPTH, bool NT, bool CM, class SE>
 __device__ __forceinline__ void plane_loop(const StepGrid& a, const Consts& k, SE se,
                                            int grp, int x0, int y0, int lane, const TileMapG& t,
                                            int64_t plane, double* s_pl, double* s_dx,
                                            const double (&rho)[R], const double (&Tm)[R],
                                            const double (&uxt)[R], const double (&uyt)[R],
-                                           const double (&t0)[R])
+                                           const double (&t0)[CM ? 1 : R], Sums<R>& acc)
 {
     constexpr int NPL = 18 / G;  // moving velocities per group
+    static_assert(18 % G == 0, "G must divide the 18 moving velocities");
     static_assert(DEPTH == 1 || NPL % 2 == 0, "two-deep pipeline needs an even plane count");
     const int gx = x0 + lane;
     const int i0 = 1 + grp * NPL, iend = i0 + NPL;
-    double A[R];  // (dt/tau) rho F_k(T) of the current speed shell
+    // (dt/tau) rho F_k(T) of the current speed shell: cached per shell, or
+    // (lean register budget of the CM variants, where rho[] holds dt/tau rho
+    // and t0[] is unused) recomputed per plane
+    double A[CM ? 1 : R];
     int kcur = -1;
     const double omct = 1.0 - a.ct;
     const GridBC g = grid_bc(a);
@@ -122,24 +172,41 @@ __device__ __forceinline__ void plane_loop(const StepGrid& a, const Consts& k, S
     //    = (1 - ct) f + (ct rho F_k) poly(eta) - cx dh^x - cy dh^y
     auto compute = [&](int i) {
         const int ks = (i - 1) / 6;
-        if (ks != kcur) {
+        if (!CM && ks != kcur) {
             kcur = ks;
 #pragma unroll
-            for (int m = 0; m < R; ++m) A[m] = (a.ct * rho[m]) * weight_c(k, ks, Tm[m]);
+            for (int m = 0; m < (CM ? 1 : R); ++m) A[m] = (a.ct * rho[m]) * weight_c(k, ks, Tm[m]);
         }
         const double vx = k.vx[i], vy = k.vy[i], eps = k.eps;
         if (vx < 0.0)
             x_pass<R, true>(s_pl, s_dx, lane, vx, eps);
         else
             x_pass<R, false>(s_pl, s_dx, lane, vx, eps);
-        __syncthreads();
+        plane_sync<Waves<G, CM>::N>();
         double* base = a.fout + i * plane + (int64_t)y0 * a.nx + x0;
+        const double hv = k.hv2[i];
         auto upd = [&](int m, double fcm, double dhy) {
             const double dhx = s_dx[m * XPITCH + lane];
             const double eta = __builtin_fma(vx, uxt[m], vy * uyt[m]);
-            double fn = __builtin_fma(omct, fcm, A[m] * feq_poly(eta, t0[m]));
+            double Am, t0m;
+            if (CM) {
+                Am = rho[m] * weight_c(k, ks, Tm[m]);
+                // 1 - |u|^2 / 2T with u = T (u/T)
+                t0m = __builtin_fma(-0.5 * Tm[m],
+                                    __builtin_fma(uxt[m], uxt[m], uyt[m] * uyt[m]), 1.0);
+            } else {
+                Am = A[m];
+                t0m = t0[m];
+            }
+            double fn = __builtin_fma(omct, fcm, Am * feq_poly(eta, t0m));
             fn = __builtin_fma(-a.cx, dhx, fn);
             fn = __builtin_fma(-a.cy, dhy, fn);
+            if (CM) {
+                acc.r[m] += fn;
+                acc.jx[m] = __builtin_fma(fn, vx, acc.jx[m]);
+                acc.jy[m] = __builtin_fma(fn, vy, acc.jy[m]);
+                acc.E[m] = __builtin_fma(fn, hv, acc.E[m]);
+            }
             double* dst = base + (int64_t)m * a.nx;
             if (!BND || (gx < a.nx && y0 + m < a.ny)) {
                 if (NT)
@@ -161,7 +228,7 @@ __device__ __forceinline__ void plane_loop(const StepGrid& a, const Consts& k, S
     double pa[Stage<R>::NPRE], pb[Stage<R>::NPRE];
     stage_load_g<R, HALO, PITCH, BND, false>(a.fin, g, k, i0, x0, y0, lane, t, plane, pa);
     stage_store_g<R, HALO, PITCH, BND, false>(g, k, se, i0, y0, lane, t, s_pl, pa);
-    __syncthreads();
+    plane_sync<Waves<G, CM>::N>();
     if (DEPTH == 2) stage_load_g<R, HALO, PITCH, BND, false>(a.fin, g, k, i0 + 1 < iend ? i0 + 1 : i0, x0, y0, lane, t, plane, pb);
 #pragma unroll 1
     for (int i = i0; i < iend; i += DEPTH) {
@@ -169,27 +236,75 @@ __device__ __forceinline__ void plane_loop(const StepGrid& a, const Consts& k, S
             stage_load_g<R, HALO, PITCH, BND, false>(a.fin, g, k, i + 1 < iend ? i + 1 : i, x0, y0, lane, t, plane, pa);
             compute(i);
             stage_store_g<R, HALO, PITCH, BND, false>(g, k, se, i + 1 < iend ? i + 1 : i, y0, lane, t, s_pl, pa);
-            __syncthreads();
+            plane_sync<Waves<G, CM>::N>();
         } else {
             stage_load_g<R, HALO, PITCH, BND, false>(a.fin, g, k, i + 2 < iend ? i + 2 : i, x0, y0, lane, t, plane, pa);
             compute(i);
             stage_store_g<R, HALO, PITCH, BND, false>(g, k, se, i + 1, y0, lane, t, s_pl, pb);
-            __syncthreads();
+            plane_sync<Waves<G, CM>::N>();
             stage_load_g<R, HALO, PITCH, BND, false>(a.fin, g, k, i + 3 < iend ? i + 3 : i, x0, y0, lane, t, plane, pb);
             compute(i + 1);
             stage_store_g<R, HALO, PITCH, BND, false>(g, k, se, i + 2 < iend ? i + 2 : i, y0, lane, t, s_pl, pa);
-            __syncthreads();
+            plane_sync<Waves<G, CM>::N>();
         }
     }
 }
 
-// One work item (tile, group) of a step. ke_dst, if not null, receives the
-// tile's (sum, max) of rho u_y^2 / 2 (group 0 only).
-template <int R, int G, int DEPTH, bool NT, class SE>
-__device__ __forceinline__ void step_work(const StepGrid& a, const Consts& k, SE se, int tile,
-                                          int grp, double* ke_dst, double* s_pl, double* s_dx)
+// Adds up the G waves' partial sums through LDS, in wave order, so that
+// every wave (or wave 0 alone, `all` false) obtains the same totals. Ends
+// with a workgroup barrier after which the LDS regions may be reused.
+template <int R, int G>
+__device__ __forceinline__ void exchange_sums(double* lds, int wave, int lane, Sums<R>& s, bool all)
 {
-    const int lane = threadIdx.x;
+    double* mine = lds + wave * WaveLds<R>::SIZE;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        mine[(0 * R + m) * 64 + lane] = s.r[m];
+        mine[(1 * R + m) * 64 + lane] = s.jx[m];
+        mine[(2 * R + m) * 64 + lane] = s.jy[m];
+        mine[(3 * R + m) * 64 + lane] = s.E[m];
+    }
+    __syncthreads();
+    if (all || wave == 0) {
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const double* p0 = lds;
+            double r = p0[(0 * R + m) * 64 + lane], jx = p0[(1 * R + m) * 64 + lane];
+            double jy = p0[(2 * R + m) * 64 + lane], E = p0[(3 * R + m) * 64 + lane];
+#pragma unroll
+            for (int w = 1; w < G; ++w) {
+                const double* p = lds + w * WaveLds<R>::SIZE;
+                r += p[(0 * R + m) * 64 + lane];
+                jx += p[(1 * R + m) * 64 + lane];
+                jy += p[(2 * R + m) * 64 + lane];
+                E += p[(3 * R + m) * 64 + lane];
+            }
+            s.r[m] = r;
+            s.jx[m] = jx;
+            s.jy[m] = jy;
+            s.E[m] = E;
+        }
+    }
+    __syncthreads();
+}
+
+// One work item of a step: tile `tile` and, for M = 0, velocity group `grp`
+// (with M = 1 the group is the wave's index). ke_dst, if not null, receives
+// the tile's (sum, max) of rho u_y^2 / 2. With CM the moment sums are read
+// from m_in and the new ones written to m_out (both [4][ny][nx]: rho, j_x,
+// j_y, E). lds holds Waves<G, CM>::N regions of WaveLds<R>::SIZE doubles.
+template <int R, int G, int DEPTH, bool NT, bool CM, class SE>
+__device__ __forceinline__ void step_work(const StepGrid& a, const Consts& k, SE se, int tile,
+                                          int grp, double* ke_dst, double* lds,
+                                          const double* __restrict__ m_in,
+                                          double* __restrict__ m_out)
+{
+    constexpr int NW = Waves<G, CM>::N;
+    const int lane = threadIdx.x & 63;
+    const int wave = NW > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
+    if (NW > 1) grp = wave;
+    double* s_pl = lds + wave * WaveLds<R>::SIZE;
+    double* s_dx = s_pl + WaveLds<R>::DX;
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
     const int x0 = tx * TX, y0 = ty * R;
     const int64_t plane = (int64_t)a.nx * a.ny;
@@ -198,33 +313,58 @@ __device__ __forceinline__ void step_work(const StepGrid& a, const Consts& k, SE
     const int gx = x0 + lane;
 
     // ---- phase 1: moments, equilibrium data, rest particle, diagnostics ----
-    double rho[R], Tm[R], uxt[R], uyt[R], t0[R];
-    double ke_s = 0.0, ke_m = 0.0;
+    Sums<R> sum;
+    double fz[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         const int gy = y0 + m;
         const bool act = gx < a.nx && gy < a.ny;
-        double r = 1.0, jx = 0.0, jy = 0.0, E = 1.0, fz = 0.0;
+        double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0, f0 = 0.0;
         if (act) {
-            const double* p = a.fin + (int64_t)gy * a.nx + x0;
-            r = 0.0;
-            E = 0.0;
+            const int64_t c = (int64_t)gy * a.nx + gx;
+            if (CM) {
+                r = m_in[c];
+                jx = m_in[plane + c];
+                jy = m_in[2 * plane + c];
+                E = m_in[3 * plane + c];
+                if (grp == 0) f0 = a.fin[c];
+            } else {
+                const double* p = a.fin + (int64_t)gy * a.nx + x0;
 #pragma unroll
-            for (int i = 0; i < NV; ++i) {
-                const double fi = (p + i * plane)[(unsigned)lane];
-                if (i == 0) fz = fi;
-                r += fi;
-                jx = __builtin_fma(fi, k.vx[i], jx);
-                jy = __builtin_fma(fi, k.vy[i], jy);
-                E = __builtin_fma(fi, k.hv2[i], E);
+                for (int i = 0; i < NV; ++i) {
+                    const double fi = (p + i * plane)[(unsigned)lane];
+                    if (i == 0) f0 = fi;
+                    r += fi;
+                    jx = __builtin_fma(fi, k.vx[i], jx);
+                    jy = __builtin_fma(fi, k.vy[i], jy);
+                    E = __builtin_fma(fi, k.hv2[i], E);
+                }
             }
         }
+        sum.r[m] = r;
+        sum.jx[m] = jx;
+        sum.jy[m] = jy;
+        sum.E[m] = E;
+        fz[m] = f0;
+    }
+
+    // rho[] holds dt/tau rho in the CM variants (see plane_loop)
+    double rho[R], Tm[R], uxt[R], uyt[R], t0[CM ? 1 : R];
+    double ke_s = 0.0, ke_m = 0.0;
+    Sums<R> acc;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const bool act = gx < a.nx && y0 + m < a.ny;
+        // idle lanes get a harmless unit state
+        const double r = act ? sum.r[m] : 1.0, E = act ? sum.E[m] : 1.0;
+        const double jx = act ? sum.jx[m] : 0.0, jy = act ? sum.jy[m] : 0.0;
         const CellEq c = cell_eq_from_sums(r, jx, jy, E);
-        rho[m] = c.rho;
+        rho[m] = CM ? a.ct * c.rho : c.rho;
         Tm[m] = c.T;
         uxt[m] = c.uxt;
         uyt[m] = c.uyt;
-        t0[m] = c.t0;
+        if (!CM) t0[m] = c.t0;
+        acc.r[m] = acc.jx[m] = acc.jy[m] = acc.E[m] = 0.0;
         if (act && grp == 0) {
             const double uy = jy / r;
             const double e = 0.5 * r * uy * uy;
@@ -234,7 +374,9 @@ __device__ __forceinline__ void step_work(const StepGrid& a, const Consts& k, SE
             const double F0 =
                 1.0 - 6.0 * (weight_c(k, 0, c.T) + weight_c(k, 1, c.T) + weight_c(k, 2, c.T));
             const double fe = c.rho * F0 * c.t0;
-            (a.fout + (int64_t)gy * a.nx + x0)[(unsigned)lane] = __builtin_fma(-a.ct, fz - fe, fz);
+            const double fn = __builtin_fma(-a.ct, fz[m] - fe, fz[m]);
+            (a.fout + (int64_t)(y0 + m) * a.nx + x0)[(unsigned)lane] = fn;
+            acc.r[m] = fn;  // v_0 = 0: the rest particle adds to rho only
         }
     }
     if (ke_dst && grp == 0) {
@@ -249,22 +391,43 @@ __device__ __forceinline__ void step_work(const StepGrid& a, const Consts& k, SE
     // ---- phase 2 ----
     const TileMapG t = tile_map_g<R, HALO, false>(grid_bc(a), x0, y0, lane, !interior);
     if (interior)
-        plane_loop<R, G, false, DEPTH, NT>(a, k, se, grp, x0, y0, lane, t, plane, s_pl, s_dx, rho,
-                                           Tm, uxt, uyt, t0);
+        plane_loop<R, G, false, DEPTH, NT, CM>(a, k, se, grp, x0, y0, lane, t, plane, s_pl, s_dx,
+                                               rho, Tm, uxt, uyt, t0, acc);
     else
-        plane_loop<R, G, true, DEPTH, NT>(a, k, se, grp, x0, y0, lane, t, plane, s_pl, s_dx, rho,
-                                          Tm, uxt, uyt, t0);
+        plane_loop<R, G, true, DEPTH, NT, CM>(a, k, se, grp, x0, y0, lane, t, plane, s_pl, s_dx,
+                                              rho, Tm, uxt, uyt, t0, acc);
+
+    // ---- phase 3: moment sums of f^{n+1} for the next step ----
+    if (CM) {
+        if (NW > 1) exchange_sums<R, NW>(lds, wave, lane, acc, false);
+        if (wave == 0) {
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                if (gx < a.nx && y0 + m < a.ny) {
+                    const int64_t c = (int64_t)(y0 + m) * a.nx + gx;
+                    m_out[c] = acc.r[m];
+                    m_out[plane + c] = acc.jx[m];
+                    m_out[2 * plane + c] = acc.jy[m];
+                    m_out[3 * plane + c] = acc.E[m];
+                }
+            }
+        }
+    }
 }
 
-// Step kernel variants: rows per lane R, velocity groups G, the
-// wavefronts-per-SIMD target W that bounds the register budget, planes in
-// flight D and non-temporal stores NT. Both the single-grid and the batched
-// kernel are instantiated for every entry, in this order.
-// Variants that the 128-register budget of W = 4 forces to spill are left
-// out: two such builds gave wrong results on a 5 x 3 grid with fixed x sides.
+// Step kernel variants: rows per lane R, velocity groups G (18/G moving
+// velocities each), the wavefronts-per-SIMD target W that bounds the register
+// budget, planes in flight D, non-temporal stores NT and carried moments M
+// (with M = 1 the G groups are the waves of one workgroup). Both the
+// single-grid and the batched kernel are instantiated for every entry, in
+// this order. Variants that the 128-register budget of W = 4 forces to spill
+// are left out: two such builds gave wrong results on a 5 x 3 grid with
+// fixed x sides.
 #define LBM_STEP_VARIANTS(X)                                                                     \
-    X(4, 1, 3, 1, 0) X(4, 3, 3, 1, 0) X(8, 2, 2, 1, 0) X(8, 1, 2, 1, 0) X(2, 3, 4, 1, 0)         \
-    X(4, 1, 3, 2, 0) X(4, 3, 3, 2, 0) X(8, 1, 2, 2, 0) X(8, 2, 2, 1, 1) X(4, 1, 3, 2, 1)         \
-    X(8, 1, 3, 1, 0)
+    X(4, 1, 3, 1, 0, 0) X(4, 3, 3, 1, 0, 0) X(8, 2, 2, 1, 0, 0) X(8, 1, 2, 1, 0, 0)               \
+    X(2, 3, 4, 1, 0, 0) X(4, 1, 3, 2, 0, 0) X(4, 3, 3, 2, 0, 0) X(8, 1, 2, 2, 0, 0)               \
+    X(8, 2, 2, 1, 1, 0) X(4, 1, 3, 2, 1, 0) X(4, 2, 3, 1, 0, 0) X(4, 3, 3, 1, 0, 1)               \
+    X(4, 2, 3, 1, 0, 1) X(4, 1, 2, 1, 0, 1) X(4, 1, 2, 2, 1, 1) X(4, 3, 2, 1, 1, 1)               \
+    X(4, 1, 2, 2, 0, 1)
 
 }  // namespace lbmd

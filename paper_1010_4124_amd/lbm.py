@@ -211,9 +211,9 @@ def lbm_step_variant_count():
 
 
 def lbm_step_variant_info(v):
-    """(rows per lane R, velocity groups G, waves-per-SIMD target W, planes in
-    flight D, non-temporal stores NT)."""
-    info = (_I * 5)()
+    """(rows per lane R, waves per tile G, waves-per-SIMD target W, planes in
+    flight D, non-temporal stores NT, carried moments M)."""
+    info = (_I * 6)()
     _check(lib().lbm_step_variant_info(int(v), info))
     return tuple(int(x) for x in info)
 
