@@ -138,17 +138,23 @@ int lbm_sep_project(lbm_ctx* ctx, const double* g, const double* A, int32_t M, c
                     double* out, lbm_stream stream);
 
 /* Step-kernel variants for the autotuner. lbm_step_variant_info fills
- * info6[0..5] = (R, G, W, D, NT, M): a workgroup of G wavefronts owns a tile
- * of 64 x R cells, each wavefront one group of 18/G moving velocities; W is
- * the wavefronts-per-SIMD target that bounds the register budget; D planes
- * are prefetched ahead of the one being computed; NT = 1 stores f^{n+1} with
- * non-temporal stores; M = 1 carries the moment sums (rho, j, E of Eq. (10))
- * from each step to the next instead of re-reading the 19 planes (a call
- * first forms them from f_in; the context holds two [4][ny][nx] sets). Every
- * variant evaluates the same formulas; results agree to rounding (the WENO
- * face arithmetic is grouped per strip of R cells and the moment sums per
- * wave), and a given variant is deterministic. lbm_set_step_variant selects
- * the variant that later lbm_step calls of that context launch. */
+ * info6[0..5] = (R, G, W, D, NT, M). Tiles are 64 x R cells; the 18 moving
+ * velocities are split into G groups; W is the wavefronts-per-SIMD target
+ * that bounds the register budget; D planes are prefetched ahead of the one
+ * being computed; NT = 1 stores f^{n+1} with non-temporal stores. M says how
+ * a tile obtains its moments (Eq. (10)):
+ *   0  every (tile, group) workgroup sums the 19 planes of f^n itself;
+ *   1  the sums rho, j, E are carried from each step to the next (a call
+ *      first forms them from f_in) and the G groups are the waves of one
+ *      workgroup;
+ *   2  a state pass per step forms the cell state (dt/tau rho, T, u/T, v/T),
+ *      updates the rest particle and the energy partials; every (tile, group)
+ *      workgroup then reads the state.
+ * The context holds two [4][ny][nx] buffers for modes 1 and 2. Every variant
+ * evaluates the same formulas; results agree to rounding (the WENO face
+ * arithmetic is grouped per strip of R cells and the moment sums per wave),
+ * and a given variant is deterministic. lbm_set_step_variant selects the
+ * variant that later lbm_step calls of that context launch. */
 int lbm_step_variant_count(void);
 int lbm_step_variant_info(int32_t variant, int32_t* info6);
 int lbm_set_step_variant(lbm_ctx* ctx, int32_t variant);

@@ -189,8 +189,8 @@ int lbm_step(lbm_ctx* c, const double* f_in, double* f_out, int32_t nsteps, doub
     const int ntiles = step_ntiles(c->variant, p.nx, p.ny);
     int info[6];
     step_variant_desc(c->variant, info);
-    const bool carried = info[5] != 0;
-    if (carried) {
+    const int mode = info[5];
+    if (mode == 1) {
         // moment sums of f_in; each step then reads one set and writes the other
         hipError_t e = launch_sums(f_in, c->msum, c->k, n, st);
         if (e != hipSuccess) return hip_fail(e, "lbm_step sums");
@@ -199,13 +199,25 @@ int lbm_step(lbm_ctx* c, const double* f_in, double* f_out, int32_t nsteps, doub
         // step s writes f_out when (nsteps - 1 - s) is even, else the scratch
         const double* src = s == 0 ? f_in : (((nsteps - s) % 2 == 0) ? f_out : c->scratch);
         double* dst = ((nsteps - 1 - s) % 2 == 0) ? f_out : c->scratch;
-        const double* m_in = carried ? c->msum + 4 * n * (s % 2) : nullptr;
-        double* m_out = carried ? c->msum + 4 * n * ((s + 1) % 2) : nullptr;
-        hipError_t e = launch_step(c->variant, src, dst, c->k, ke_log ? c->ke_part : nullptr,
-                                   p.nx, p.ny, p.bc, cx, cy, ct, m_in, m_out, st);
+        const double* m_in = nullptr;
+        double* m_out = nullptr;
+        int nparts = ntiles;
+        if (mode == 1) {
+            m_in = c->msum + 4 * n * (s % 2);
+            m_out = c->msum + 4 * n * ((s + 1) % 2);
+        } else if (mode == 2) {
+            // state pass: cell state, rest particle and energy partials
+            hipError_t e = launch_state(src, dst, c->msum, n, ct, ke_log ? c->ke_part : nullptr,
+                                        &nparts, c->k, st);
+            if (e != hipSuccess) return hip_fail(e, "lbm_step state");
+            m_in = c->msum;
+        }
+        hipError_t e = launch_step(c->variant, src, dst, c->k,
+                                   ke_log && mode != 2 ? c->ke_part : nullptr, p.nx, p.ny, p.bc,
+                                   cx, cy, ct, m_in, m_out, st);
         if (e != hipSuccess) return hip_fail(e, "lbm_step");
         if (ke_log) {
-            e = launch_reduce_pairs(c->ke_part, ntiles, p.dx * p.dy, ke_log + 2 * s, st);
+            e = launch_reduce_pairs(c->ke_part, nparts, p.dx * p.dy, ke_log + 2 * s, st);
             if (e != hipSuccess) return hip_fail(e, "lbm_step ke");
         }
     }

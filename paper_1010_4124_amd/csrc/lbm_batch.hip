@@ -39,7 +39,9 @@ struct BatchInst {
     int bc[4];
     int tiles_x;
     int ntiles;      // tiles of the current variant
-    int ke_off;      // first (sum, max) partial of the instance
+    int ke_off;      // first per-tile (sum, max) partial of the instance
+    int kp_off, kp_n;  // partials the energy reduction adds up: per tile, or per
+                       // 256-cell block when a state pass forms them
     int pad_;
     double cx, cy, ct, dxdy;
     double side_eq[4 * NV];  // fixed-side equilibria [side][i]
@@ -57,11 +59,11 @@ struct BatchArgs {
     Consts k;
 };
 
-template <int R, int G, int W, int DEPTH, bool NT, bool CM>
-__global__ __launch_bounds__((64 * Waves<G, CM>::N)) __attribute__((amdgpu_waves_per_eu(W)))
+template <int R, int G, int W, int DEPTH, bool NT, int MODE>
+__global__ __launch_bounds__((64 * Waves<G, MODE>::N)) __attribute__((amdgpu_waves_per_eu(W)))
 void k_step_batch(BatchArgs a)
 {
-    __shared__ double lds[Waves<G, CM>::N * WaveLds<R>::SIZE];
+    __shared__ double lds[Waves<G, MODE>::N * WaveLds<R>::SIZE];
 
     const int b = blockIdx.x;
     const int lo = (b & 7) * a.per_xcd;
@@ -82,12 +84,13 @@ void k_step_batch(BatchArgs a)
         s.cx = d.cx;
         s.cy = d.cy;
         s.ct = d.ct;
-        constexpr int GW = CM ? 1 : G;
+        constexpr int GW = MODE == PH_CARRY ? 1 : G;
         const int tile = it.y / GW, grp = it.y - tile * GW;
-        step_work<R, G, DEPTH, NT, CM>(
+        step_work<R, G, DEPTH, NT, MODE>(
             s, a.k, SideEqPtr{d.side_eq}, tile, grp,
             a.ke_part ? a.ke_part + 2 * ((int64_t)d.ke_off + tile) : nullptr, lds,
-            CM ? a.m_in + d.moff : nullptr, CM ? a.m_out + d.moff : nullptr);
+            MODE != PH_SUMS ? a.m_in + d.moff : nullptr,
+            MODE == PH_CARRY ? a.m_out + d.moff : nullptr);
         __syncthreads();  // LDS is reused by the next item
     }
 }
@@ -101,9 +104,9 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const double* __restrict__
 {
     __shared__ double sr[8];
     const BatchInst& d = inst[blockIdx.x];
-    const double* p = part + 2 * (int64_t)d.ke_off;
+    const double* p = part + 2 * (int64_t)d.kp_off;
     double s = 0.0, mx = 0.0;
-    for (int j = threadIdx.x; j < d.ntiles; j += 256) {
+    for (int j = threadIdx.x; j < d.kp_n; j += 256) {
         s += p[2 * j];
         mx = fmax(mx, p[2 * j + 1]);
     }
@@ -126,7 +129,11 @@ struct BatchVariant {
     int R, G, M;
     void (*kernel)(BatchArgs);
 };
-#define LBM_BATCH_VARIANT(R, G, W, D, NT, M) {R, G, M, k_step_batch<R, G, W, D, NT, M>},
+// The batched kernel keeps an instance descriptor live as well: where the
+// single-grid variant targets four or more waves per SIMD it gets one wave
+// less, so that no instantiation has to spill.
+#define LBM_BATCH_VARIANT(R, G, W, D, NT, M) \
+    {R, G, M, k_step_batch<R, G, ((W) >= 4 ? (W) - 1 : (W)), D, NT, M>},
 static const BatchVariant kBatchVariants[] = {LBM_STEP_VARIANTS(LBM_BATCH_VARIANT)};
 #undef LBM_BATCH_VARIANT
 
@@ -191,21 +198,26 @@ void drop_graphs(lbm_batch* b)
 int build_tables(lbm_batch* b)
 {
     const BatchVariant& V = kBatchVariants[b->variant];
-    int64_t nwork = 0, ntiles = 0;
+    const int per_tile = V.M == PH_CARRY ? 1 : V.G;  // work items per tile
+    int64_t nwork = 0, ntiles = 0, nblk = 0;
     for (int i = 0; i < b->n; ++i) {
         BatchInst& d = b->hinst[i];
         d.tiles_x = (d.nx + TX - 1) / TX;
         d.ntiles = d.tiles_x * ((d.ny + V.R - 1) / V.R);
         d.ke_off = (int)ntiles;
+        const int blocks = (int)(((int64_t)d.nx * d.ny + 255) / 256);
+        d.kp_off = V.M == PH_STATE ? (int)nblk : d.ke_off;
+        d.kp_n = V.M == PH_STATE ? blocks : d.ntiles;
         ntiles += d.ntiles;
-        nwork += (int64_t)d.ntiles * (V.M ? 1 : V.G);
+        nblk += blocks;
+        nwork += (int64_t)d.ntiles * per_tile;
     }
-    if (nwork > b->work_cap || ntiles > b->ke_cap)
+    if (nwork > b->work_cap || ntiles > b->ke_cap || nblk > b->ke_cap)
         return bfail(LBM_EINVAL, "batch work list exceeds its allocation");
     std::vector<int2> w((size_t)nwork);
     size_t q = 0;
     for (int i = 0; i < b->n; ++i)
-        for (int t = 0; t < b->hinst[i].ntiles * (V.M ? 1 : V.G); ++t) w[q++] = make_int2(i, t);
+        for (int t = 0; t < b->hinst[i].ntiles * per_tile; ++t) w[q++] = make_int2(i, t);
     hipError_t e;
     if ((e = hipMemcpy(b->inst, b->hinst.data(), sizeof(BatchInst) * b->n,
                        hipMemcpyHostToDevice)) != hipSuccess ||
@@ -223,18 +235,35 @@ hipError_t launch_batch_step(lbm_batch* b, const double* src, double* dst, bool 
 {
     const BatchVariant& V = kBatchVariants[b->variant];
     BatchArgs a;
-    a.m_in = V.M ? b->msum + 4 * b->cells * parity : nullptr;
-    a.m_out = V.M ? b->msum + 4 * b->cells * (1 - parity) : nullptr;
+    a.m_in = nullptr;
+    a.m_out = nullptr;
+    if (V.M == PH_CARRY) {
+        a.m_in = b->msum + 4 * b->cells * parity;
+        a.m_out = b->msum + 4 * b->cells * (1 - parity);
+    } else if (V.M == PH_STATE) {
+        // state pass per instance: cell state, rest particle, energy partials
+        for (int i = 0; i < b->n; ++i) {
+            const BatchInst& d = b->hinst[i];
+            int np = 0;
+            hipError_t e = launch_state(src + d.off, dst + d.off, b->msum + d.moff,
+                                        (int64_t)d.nx * d.ny, d.ct,
+                                        ke ? b->ke_part + 2 * (int64_t)d.kp_off : nullptr, &np,
+                                        b->k, st);
+            if (e != hipSuccess) return e;
+        }
+        a.m_in = b->msum;
+    }
     a.fin = src;
     a.fout = dst;
-    a.ke_part = ke ? b->ke_part : nullptr;
+    a.ke_part = ke && V.M != PH_STATE ? b->ke_part : nullptr;
     a.inst = b->inst;
     a.work = b->work;
     a.nwork = b->nwork;
     a.per_xcd = (b->nwork + 7) / 8;
     a.slots = b->slots > 0 ? std::min(b->slots, a.per_xcd) : a.per_xcd;
     a.k = b->k;
-    hipLaunchKernelGGL(V.kernel, dim3(8 * a.slots), dim3(64 * (V.M ? V.G : 1)), 0, st, a);
+    hipLaunchKernelGGL(V.kernel, dim3(8 * a.slots), dim3(64 * (V.M == PH_CARRY ? V.G : 1)), 0, st,
+                       a);
     return hipGetLastError();
 }
 
@@ -366,11 +395,14 @@ int lbm_batch_create(const lbm_params* inst, int32_t n, const int64_t* f_offset,
             const int64_t nt = (int64_t)((inst[i].nx + TX - 1) / TX) *
                                ((inst[i].ny + kBatchVariants[v].R - 1) / kBatchVariants[v].R);
             t += nt;
-            w += nt * (kBatchVariants[v].M ? 1 : kBatchVariants[v].G);
+            w += nt * (kBatchVariants[v].M == PH_CARRY ? 1 : kBatchVariants[v].G);
         }
         wmax = std::max(wmax, w);
         tmax = std::max(tmax, t);
     }
+    int64_t blocks = 0;
+    for (int i = 0; i < n; ++i) blocks += ((int64_t)inst[i].nx * inst[i].ny + 255) / 256;
+    tmax = std::max(tmax, blocks);
     if (wmax >= (1ll << 31) || tmax >= (1ll << 30)) {
         delete b;
         return bfail(LBM_EINVAL, "batch too large");
@@ -492,7 +524,7 @@ int lbm_batch_step(lbm_batch* b, const double* f_in, double* f_out, int32_t nste
     const bool ke = ke_log != nullptr;
     // step s writes f_out when (nsteps - 1 - s) is even, else the scratch
     auto dst_of = [&](int s) { return ((nsteps - 1 - s) % 2 == 0) ? f_out : b->scratch; };
-    if (kBatchVariants[b->variant].M) {
+    if (kBatchVariants[b->variant].M == PH_CARRY) {
         // moment sums of f_in for the first step (set 0)
         for (int i = 0; i < b->n; ++i) {
             hipError_t e = launch_sums(f_in + b->off[i], b->msum + 4 * b->cell_off[i], b->k,

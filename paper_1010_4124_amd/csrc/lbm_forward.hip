@@ -27,20 +27,70 @@ struct StepArgs {
     Consts k;
 };
 
-template <int R, int G, int W, int DEPTH, bool NT, bool CM>
-__global__ __launch_bounds__((64 * Waves<G, CM>::N)) __attribute__((amdgpu_waves_per_eu(W)))
+template <int R, int G, int W, int DEPTH, bool NT, int MODE>
+__global__ __launch_bounds__((64 * Waves<G, MODE>::N)) __attribute__((amdgpu_waves_per_eu(W)))
 void k_step(StepArgs a)
 {
-    __shared__ double lds[Waves<G, CM>::N * WaveLds<R>::SIZE];
+    __shared__ double lds[Waves<G, MODE>::N * WaveLds<R>::SIZE];
 
     const int b = blockIdx.x;
     const int work = (b & 7) * a.per_xcd + (b >> 3);
     if (work >= a.nwork) return;
-    constexpr int GW = CM ? 1 : G;  // groups per work item's tile index
+    constexpr int GW = MODE == PH_CARRY ? 1 : G;  // groups per work item's tile index
     const int tile = work / GW, grp = work - tile * GW;
-    step_work<R, G, DEPTH, NT, CM>(a.s, a.k, SideEqConsts{}, tile, grp,
+    step_work<R, G, DEPTH, NT, MODE>(a.s, a.k, SideEqConsts{}, tile, grp,
                                    a.ke_part ? a.ke_part + 2 * tile : nullptr, lds, a.m_in,
                                    a.m_out);
+}
+
+// State pass of the PH_STATE variants, one thread per cell: the moments of
+// Eq. (10) summed over the 19 planes in the order phase 1 uses, the cell
+// state (dt/tau rho, T, u/T, v/T) for the step kernel, the rest particle's
+// update (no convection: f_0' = f_0 - dt/tau (f_0 - rho F_0 (1 - u^2/2T)))
+// and per-block (sum, max) partials of rho u_y^2 / 2.
+__global__ __launch_bounds__(256) void k_state(const double* __restrict__ f,
+                                               double* __restrict__ fout,
+                                               double* __restrict__ st, int64_t n, double ct,
+                                               double* __restrict__ part, Consts k)
+{
+    __shared__ double sr[8];
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double e = 0.0;
+    if (c < n) {
+        double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
+        const double f0 = f[c];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const double fi = f[i * n + c];
+            r += fi;
+            jx = __builtin_fma(fi, k.vx[i], jx);
+            jy = __builtin_fma(fi, k.vy[i], jy);
+            E = __builtin_fma(fi, k.hv2[i], E);
+        }
+        const CellEq q = cell_eq_from_sums(r, jx, jy, E);
+        const double F0 =
+            1.0 - 6.0 * (weight_c(k, 0, q.T) + weight_c(k, 1, q.T) + weight_c(k, 2, q.T));
+        const double fe = q.rho * F0 * q.t0;
+        fout[c] = __builtin_fma(-ct, f0 - fe, f0);
+        st[c] = ct * q.rho;
+        st[n + c] = q.T;
+        st[2 * n + c] = q.uxt;
+        st[3 * n + c] = q.uyt;
+        const double uy = jy / r;
+        e = 0.5 * r * uy * uy;
+    }
+    if (!part) return;
+    const double s = wave_sum(e), mx = wave_max(e);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sr[2 * w] = s;
+        sr[2 * w + 1] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sr[0] + sr[2] + sr[4] + sr[6];
+        part[2 * blockIdx.x + 1] = fmax(fmax(sr[1], sr[3]), fmax(sr[5], sr[7]));
+    }
 }
 
 // Moment sums rho, j_x, j_y, E (Eq. (10)) per cell, in the order the step
@@ -240,10 +290,21 @@ hipError_t launch_step(int variant, const double* fin, double* fout, const Const
     a.ke_part = ke_part;
     a.m_in = m_in;
     a.m_out = m_out;
-    a.nwork = a.s.tiles_x * ((ny + V.R - 1) / V.R) * (V.M ? 1 : V.G);
+    a.nwork = a.s.tiles_x * ((ny + V.R - 1) / V.R) * (V.M == PH_CARRY ? 1 : V.G);
     a.per_xcd = (a.nwork + 7) / 8;
     a.k = k;
-    hipLaunchKernelGGL(V.kernel, dim3(8 * a.per_xcd), dim3(64 * (V.M ? V.G : 1)), 0, st, a);
+    hipLaunchKernelGGL(V.kernel, dim3(8 * a.per_xcd), dim3(64 * (V.M == PH_CARRY ? V.G : 1)), 0,
+                       st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_state(const double* f, double* fout, double* state, int64_t n, double ct,
+                        double* part, int* nparts, const Consts& k, hipStream_t st)
+{
+    const int64_t blocks = (n + 255) / 256;
+    *nparts = (int)blocks;
+    hipLaunchKernelGGL(k_state, dim3((unsigned)blocks), dim3(256), 0, st, f, fout, state, n, ct,
+                       part, k);
     return hipGetLastError();
 }
 

@@ -34,6 +34,8 @@ hipError_t launch_step(int variant, const double* fin, double* fout, const Const
                        double* ke_part, int nx, int ny, const int bc[4], double cx, double cy,
                        double ct, const double* m_in, double* m_out, hipStream_t st);
 hipError_t launch_sums(const double* f, double* m, const Consts& k, int64_t n, hipStream_t st);
+hipError_t launch_state(const double* f, double* fout, double* state, int64_t n, double ct,
+                        double* part, int* nparts, const Consts& k, hipStream_t st);
 hipError_t launch_reduce_pairs(const double* part, int n, double dxdy, double* out2,
                                hipStream_t st);
 hipError_t launch_init(const double* rho, const double* ux, const double* uy, const double* T,

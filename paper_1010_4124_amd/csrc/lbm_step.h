@@ -109,11 +109,18 @@ struct WaveLds {
     static constexpr int SIZE = WORK > XCH ? WORK : XCH;
 };
 
+// How phase 1 obtains the tile's moments.
+enum {
+    PH_SUMS = 0,   // sum the 19 planes of f^n
+    PH_CARRY = 1,  // read the sums rho, j, E the previous step wrote
+    PH_STATE = 2,  // read the cell state (dt/tau rho, T, u/T, v/T) a state pass wrote
+};
+
 // Waves per workgroup of a variant: the G groups are waves of one workgroup
 // only with carried moments.
-template <int G, bool CM>
+template <int G, int MODE>
 struct Waves {
-    static constexpr int N = CM ? G : 1;
+    static constexpr int N = MODE == PH_CARRY ? G : 1;
 };
 
 // Orders one wave's LDS accesses between the staging, x-pass and y-pass of a
@@ -147,23 +154,26 @@ struct Sums {
 // re-read) and consumed after the current plane's stores, so waiting for a
 // staged plane never waits for stores. With CM the sums of the new values
 // are accumulated into `acc`.
-template <int R, int G, bool BND, int DEPTH, bool NT, bool CM, class SE>
+template <int R, int G, bool BND, int DEPTH, bool NT, int MODE, class SE>
 __device__ __forceinline__ void plane_loop(const StepGrid& a, const Consts& k, SE se,
                                            int grp, int x0, int y0, int lane, const TileMapG& t,
                                            int64_t plane, double* s_pl, double* s_dx,
                                            const double (&rho)[R], const double (&Tm)[R],
                                            const double (&uxt)[R], const double (&uyt)[R],
-                                           const double (&t0)[CM ? 1 : R], Sums<R>& acc)
+                                           const double (&t0)[MODE != PH_SUMS ? 1 : R],
+                                           Sums<R>& acc)
 {
+    constexpr bool CM = MODE == PH_CARRY;     // accumulate the new moment sums
+    constexpr bool LEAN = MODE != PH_SUMS;    // rho[] = dt/tau rho, no t0[], no A cache
     constexpr int NPL = 18 / G;  // moving velocities per group
     static_assert(18 % G == 0, "G must divide the 18 moving velocities");
     static_assert(DEPTH == 1 || NPL % 2 == 0, "two-deep pipeline needs an even plane count");
     const int gx = x0 + lane;
     const int i0 = 1 + grp * NPL, iend = i0 + NPL;
     // (dt/tau) rho F_k(T) of the current speed shell: cached per shell, or
-    // (lean register budget of the CM variants, where rho[] holds dt/tau rho
-    // and t0[] is unused) recomputed per plane
-    double A[CM ? 1 : R];
+    // (lean register budget, where rho[] holds dt/tau rho and t0[] is
+    // unused) recomputed per plane
+    double A[LEAN ? 1 : R];
     int kcur = -1;
     const double omct = 1.0 - a.ct;
     const GridBC g = grid_bc(a);
@@ -172,24 +182,24 @@ __device__ __forceinline__ void plane_loop(const StepGrid& a, const Consts& k, S
     //    = (1 - ct) f + (ct rho F_k) poly(eta) - cx dh^x - cy dh^y
     auto compute = [&](int i) {
         const int ks = (i - 1) / 6;
-        if (!CM && ks != kcur) {
+        if (!LEAN && ks != kcur) {
             kcur = ks;
 #pragma unroll
-            for (int m = 0; m < (CM ? 1 : R); ++m) A[m] = (a.ct * rho[m]) * weight_c(k, ks, Tm[m]);
+            for (int m = 0; m < (LEAN ? 1 : R); ++m) A[m] = (a.ct * rho[m]) * weight_c(k, ks, Tm[m]);
         }
         const double vx = k.vx[i], vy = k.vy[i], eps = k.eps;
         if (vx < 0.0)
             x_pass<R, true>(s_pl, s_dx, lane, vx, eps);
         else
             x_pass<R, false>(s_pl, s_dx, lane, vx, eps);
-        plane_sync<Waves<G, CM>::N>();
+        plane_sync<Waves<G, MODE>::N>();
         double* base = a.fout + i * plane + (int64_t)y0 * a.nx + x0;
         const double hv = k.hv2[i];
         auto upd = [&](int m, double fcm, double dhy) {
             const double dhx = s_dx[m * XPITCH + lane];
             const double eta = __builtin_fma(vx, uxt[m], vy * uyt[m]);
             double Am, t0m;
-            if (CM) {
+            if (LEAN) {
                 Am = rho[m] * weight_c(k, ks, Tm[m]);
                 // 1 - |u|^2 / 2T with u = T (u/T)
                 t0m = __builtin_fma(-0.5 * Tm[m],
@@ -228,7 +238,11 @@ __device__ __forceinline__ void plane_loop(const StepGrid& a, const Consts& k, S
     double pa[Stage<R>::NPRE], pb[Stage<R>::NPRE];
     stage_load_g<R, HALO, PITCH, BND, false>(a.fin, g, k, i0, x0, y0, lane, t, plane, pa);
     stage_store_g<R, HALO, PITCH, BND, false>(g, k, se, i0, y0, lane, t, s_pl, pa);
-    plane_sync<Waves<G, CM>::N>();
+    plane_sync<Waves<G, MODE>::N>();
+    if constexpr (NPL == 1) {
+        compute(i0);
+        return;
+    }
     if (DEPTH == 2) stage_load_g<R, HALO, PITCH, BND, false>(a.fin, g, k, i0 + 1 < iend ? i0 + 1 : i0, x0, y0, lane, t, plane, pb);
 #pragma unroll 1
     for (int i = i0; i < iend; i += DEPTH) {
@@ -236,16 +250,16 @@ __device__ __forceinline__ void plane_loop(const StepGrid& a, const Consts& k, S
             stage_load_g<R, HALO, PITCH, BND, false>(a.fin, g, k, i + 1 < iend ? i + 1 : i, x0, y0, lane, t, plane, pa);
             compute(i);
             stage_store_g<R, HALO, PITCH, BND, false>(g, k, se, i + 1 < iend ? i + 1 : i, y0, lane, t, s_pl, pa);
-            plane_sync<Waves<G, CM>::N>();
+            plane_sync<Waves<G, MODE>::N>();
         } else {
             stage_load_g<R, HALO, PITCH, BND, false>(a.fin, g, k, i + 2 < iend ? i + 2 : i, x0, y0, lane, t, plane, pa);
             compute(i);
             stage_store_g<R, HALO, PITCH, BND, false>(g, k, se, i + 1, y0, lane, t, s_pl, pb);
-            plane_sync<Waves<G, CM>::N>();
+            plane_sync<Waves<G, MODE>::N>();
             stage_load_g<R, HALO, PITCH, BND, false>(a.fin, g, k, i + 3 < iend ? i + 3 : i, x0, y0, lane, t, plane, pb);
             compute(i + 1);
             stage_store_g<R, HALO, PITCH, BND, false>(g, k, se, i + 2 < iend ? i + 2 : i, y0, lane, t, s_pl, pa);
-            plane_sync<Waves<G, CM>::N>();
+            plane_sync<Waves<G, MODE>::N>();
         }
     }
 }
@@ -288,18 +302,21 @@ __device__ __forceinline__ void exchange_sums(double* lds, int wave, int lane, S
     __syncthreads();
 }
 
-// One work item of a step: tile `tile` and, for M = 0, velocity group `grp`
-// (with M = 1 the group is the wave's index). ke_dst, if not null, receives
-// the tile's (sum, max) of rho u_y^2 / 2. With CM the moment sums are read
-// from m_in and the new ones written to m_out (both [4][ny][nx]: rho, j_x,
-// j_y, E). lds holds Waves<G, CM>::N regions of WaveLds<R>::SIZE doubles.
-template <int R, int G, int DEPTH, bool NT, bool CM, class SE>
+// One work item of a step: tile `tile` and, unless the moments are carried,
+// velocity group `grp` (with carried moments the group is the wave's index).
+// ke_dst, if not null, receives the tile's (sum, max) of rho u_y^2 / 2.
+// m_in / m_out: PH_CARRY reads and writes the moment sums (rho, j_x, j_y, E,
+// each [ny][nx]); PH_STATE reads the cell state (dt/tau rho, T, u/T, v/T)
+// and leaves the rest particle and the diagnostics to the state pass. lds
+// holds Waves<G, MODE>::N regions of WaveLds<R>::SIZE doubles.
+template <int R, int G, int DEPTH, bool NT, int MODE, class SE>
 __device__ __forceinline__ void step_work(const StepGrid& a, const Consts& k, SE se, int tile,
                                           int grp, double* ke_dst, double* lds,
                                           const double* __restrict__ m_in,
                                           double* __restrict__ m_out)
 {
-    constexpr int NW = Waves<G, CM>::N;
+    constexpr bool CM = MODE == PH_CARRY, PS = MODE == PH_STATE, LEAN = MODE != PH_SUMS;
+    constexpr int NW = Waves<G, MODE>::N;
     const int lane = threadIdx.x & 63;
     const int wave = NW > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
     if (NW > 1) grp = wave;
@@ -313,89 +330,102 @@ __device__ __forceinline__ void step_work(const StepGrid& a, const Consts& k, SE
     const int gx = x0 + lane;
 
     // ---- phase 1: moments, equilibrium data, rest particle, diagnostics ----
-    Sums<R> sum;
-    double fz[R];
-#pragma unroll
-    for (int m = 0; m < R; ++m) {
-        const int gy = y0 + m;
-        const bool act = gx < a.nx && gy < a.ny;
-        double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0, f0 = 0.0;
-        if (act) {
-            const int64_t c = (int64_t)gy * a.nx + gx;
-            if (CM) {
-                r = m_in[c];
-                jx = m_in[plane + c];
-                jy = m_in[2 * plane + c];
-                E = m_in[3 * plane + c];
-                if (grp == 0) f0 = a.fin[c];
-            } else {
-                const double* p = a.fin + (int64_t)gy * a.nx + x0;
-#pragma unroll
-                for (int i = 0; i < NV; ++i) {
-                    const double fi = (p + i * plane)[(unsigned)lane];
-                    if (i == 0) f0 = fi;
-                    r += fi;
-                    jx = __builtin_fma(fi, k.vx[i], jx);
-                    jy = __builtin_fma(fi, k.vy[i], jy);
-                    E = __builtin_fma(fi, k.hv2[i], E);
-                }
-            }
-        }
-        sum.r[m] = r;
-        sum.jx[m] = jx;
-        sum.jy[m] = jy;
-        sum.E[m] = E;
-        fz[m] = f0;
-    }
-
-    // rho[] holds dt/tau rho in the CM variants (see plane_loop)
-    double rho[R], Tm[R], uxt[R], uyt[R], t0[CM ? 1 : R];
-    double ke_s = 0.0, ke_m = 0.0;
+    // rho[] holds dt/tau rho in the lean modes (see plane_loop)
+    double rho[R], Tm[R], uxt[R], uyt[R], t0[LEAN ? 1 : R];
     Sums<R> acc;
 #pragma unroll
-    for (int m = 0; m < R; ++m) {
-        const bool act = gx < a.nx && y0 + m < a.ny;
-        // idle lanes get a harmless unit state
-        const double r = act ? sum.r[m] : 1.0, E = act ? sum.E[m] : 1.0;
-        const double jx = act ? sum.jx[m] : 0.0, jy = act ? sum.jy[m] : 0.0;
-        const CellEq c = cell_eq_from_sums(r, jx, jy, E);
-        rho[m] = CM ? a.ct * c.rho : c.rho;
-        Tm[m] = c.T;
-        uxt[m] = c.uxt;
-        uyt[m] = c.uyt;
-        if (!CM) t0[m] = c.t0;
-        acc.r[m] = acc.jx[m] = acc.jy[m] = acc.E[m] = 0.0;
-        if (act && grp == 0) {
-            const double uy = jy / r;
-            const double e = 0.5 * r * uy * uy;
-            ke_s += e;
-            ke_m = fmax(ke_m, e);
-            // rest particle: no convection, f^eq_0 = rho F_0 (1 - u^2/2T)
-            const double F0 =
-                1.0 - 6.0 * (weight_c(k, 0, c.T) + weight_c(k, 1, c.T) + weight_c(k, 2, c.T));
-            const double fe = c.rho * F0 * c.t0;
-            const double fn = __builtin_fma(-a.ct, fz[m] - fe, fz[m]);
-            (a.fout + (int64_t)(y0 + m) * a.nx + x0)[(unsigned)lane] = fn;
-            acc.r[m] = fn;  // v_0 = 0: the rest particle adds to rho only
+    for (int m = 0; m < R; ++m) acc.r[m] = acc.jx[m] = acc.jy[m] = acc.E[m] = 0.0;
+    if constexpr (PS) {
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const bool act = gx < a.nx && y0 + m < a.ny;
+            const int64_t c = (int64_t)(y0 + m) * a.nx + gx;
+            rho[m] = act ? m_in[c] : a.ct;  // idle lanes: unit state
+            Tm[m] = act ? m_in[plane + c] : 1.0;
+            uxt[m] = act ? m_in[2 * plane + c] : 0.0;
+            uyt[m] = act ? m_in[3 * plane + c] : 0.0;
         }
-    }
-    if (ke_dst && grp == 0) {
-        ke_s = wave_sum(ke_s);
-        ke_m = wave_max(ke_m);
-        if (lane == 0) {
-            ke_dst[0] = ke_s;
-            ke_dst[1] = ke_m;
+    } else {
+        Sums<R> sum;
+        double fz[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int gy = y0 + m;
+            const bool act = gx < a.nx && gy < a.ny;
+            double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0, f0 = 0.0;
+            if (act) {
+                const int64_t c = (int64_t)gy * a.nx + gx;
+                if (CM) {
+                    r = m_in[c];
+                    jx = m_in[plane + c];
+                    jy = m_in[2 * plane + c];
+                    E = m_in[3 * plane + c];
+                    if (grp == 0) f0 = a.fin[c];
+                } else {
+                    const double* p = a.fin + (int64_t)gy * a.nx + x0;
+#pragma unroll
+                    for (int i = 0; i < NV; ++i) {
+                        const double fi = (p + i * plane)[(unsigned)lane];
+                        if (i == 0) f0 = fi;
+                        r += fi;
+                        jx = __builtin_fma(fi, k.vx[i], jx);
+                        jy = __builtin_fma(fi, k.vy[i], jy);
+                        E = __builtin_fma(fi, k.hv2[i], E);
+                    }
+                }
+            }
+            sum.r[m] = r;
+            sum.jx[m] = jx;
+            sum.jy[m] = jy;
+            sum.E[m] = E;
+            fz[m] = f0;
+        }
+
+        double ke_s = 0.0, ke_m = 0.0;
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const bool act = gx < a.nx && y0 + m < a.ny;
+            // idle lanes get a harmless unit state
+            const double r = act ? sum.r[m] : 1.0, E = act ? sum.E[m] : 1.0;
+            const double jx = act ? sum.jx[m] : 0.0, jy = act ? sum.jy[m] : 0.0;
+            const CellEq c = cell_eq_from_sums(r, jx, jy, E);
+            rho[m] = LEAN ? a.ct * c.rho : c.rho;
+            Tm[m] = c.T;
+            uxt[m] = c.uxt;
+            uyt[m] = c.uyt;
+            if (!LEAN) t0[m] = c.t0;
+            if (act && grp == 0) {
+                const double uy = jy / r;
+                const double e = 0.5 * r * uy * uy;
+                ke_s += e;
+                ke_m = fmax(ke_m, e);
+                // rest particle: no convection, f^eq_0 = rho F_0 (1 - u^2/2T)
+                const double F0 = 1.0 - 6.0 * (weight_c(k, 0, c.T) + weight_c(k, 1, c.T) +
+                                               weight_c(k, 2, c.T));
+                const double fe = c.rho * F0 * c.t0;
+                const double fn = __builtin_fma(-a.ct, fz[m] - fe, fz[m]);
+                (a.fout + (int64_t)(y0 + m) * a.nx + x0)[(unsigned)lane] = fn;
+                acc.r[m] = fn;  // v_0 = 0: the rest particle adds to rho only
+            }
+        }
+        if (ke_dst && grp == 0) {
+            ke_s = wave_sum(ke_s);
+            ke_m = wave_max(ke_m);
+            if (lane == 0) {
+                ke_dst[0] = ke_s;
+                ke_dst[1] = ke_m;
+            }
         }
     }
 
     // ---- phase 2 ----
     const TileMapG t = tile_map_g<R, HALO, false>(grid_bc(a), x0, y0, lane, !interior);
     if (interior)
-        plane_loop<R, G, false, DEPTH, NT, CM>(a, k, se, grp, x0, y0, lane, t, plane, s_pl, s_dx,
-                                               rho, Tm, uxt, uyt, t0, acc);
+        plane_loop<R, G, false, DEPTH, NT, MODE>(a, k, se, grp, x0, y0, lane, t, plane, s_pl,
+                                                 s_dx, rho, Tm, uxt, uyt, t0, acc);
     else
-        plane_loop<R, G, true, DEPTH, NT, CM>(a, k, se, grp, x0, y0, lane, t, plane, s_pl, s_dx,
-                                              rho, Tm, uxt, uyt, t0, acc);
+        plane_loop<R, G, true, DEPTH, NT, MODE>(a, k, se, grp, x0, y0, lane, t, plane, s_pl,
+                                                s_dx, rho, Tm, uxt, uyt, t0, acc);
 
     // ---- phase 3: moment sums of f^{n+1} for the next step ----
     if (CM) {
@@ -417,8 +447,9 @@ __device__ __forceinline__ void step_work(const StepGrid& a, const Consts& k, SE
 
 // Step kernel variants: rows per lane R, velocity groups G (18/G moving
 // velocities each), the wavefronts-per-SIMD target W that bounds the register
-// budget, planes in flight D, non-temporal stores NT and carried moments M
-// (with M = 1 the G groups are the waves of one workgroup). Both the
+// budget, planes in flight D, non-temporal stores NT and the phase-1 mode M
+// (PH_SUMS, PH_CARRY: the G groups are the waves of one workgroup, PH_STATE:
+// a state pass runs first). Both the
 // single-grid and the batched kernel are instantiated for every entry, in
 // this order. Variants that the 128-register budget of W = 4 forces to spill
 // are left out: two such builds gave wrong results on a 5 x 3 grid with
@@ -428,6 +459,8 @@ __device__ __forceinline__ void step_work(const StepGrid& a, const Consts& k, SE
     X(2, 3, 4, 1, 0, 0) X(4, 1, 3, 2, 0, 0) X(4, 3, 3, 2, 0, 0) X(8, 1, 2, 2, 0, 0)               \
     X(8, 2, 2, 1, 1, 0) X(4, 1, 3, 2, 1, 0) X(4, 2, 3, 1, 0, 0) X(4, 3, 3, 1, 0, 1)               \
     X(4, 2, 3, 1, 0, 1) X(4, 1, 2, 1, 0, 1) X(4, 1, 2, 2, 1, 1) X(4, 3, 2, 1, 1, 1)               \
-    X(4, 1, 2, 2, 0, 1)
+    X(4, 1, 2, 2, 0, 1) X(4, 18, 4, 1, 0, 2) X(2, 18, 5, 1, 0, 2) X(8, 18, 3, 1, 0, 2)            \
+    X(4, 3, 3, 1, 0, 2) X(2, 9, 4, 1, 0, 2) X(2, 6, 4, 1, 0, 2) X(4, 9, 3, 1, 0, 2)               \
+    X(4, 6, 3, 1, 0, 2)
 
 }  // namespace lbmd

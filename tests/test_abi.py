@@ -26,8 +26,8 @@ def test_version_and_variants_without_gpu():
     assert n >= 2
     for v in range(n):
         R, G, W, D, NT, M = lbm.lbm_step_variant_info(v)
-        assert R in (1, 2, 4, 8) and G in (1, 2, 3, 6) and W >= 1 and D in (1, 2)
-        assert NT in (0, 1) and M in (0, 1) and 18 % G == 0
+        assert R in (1, 2, 4, 8) and G in (1, 2, 3, 6, 9, 18) and W >= 1 and D in (1, 2)
+        assert NT in (0, 1) and M in (0, 1, 2) and 18 % G == 0
     with pytest.raises(lbm.LbmError):
         lbm.lbm_step_variant_info(n)
 
