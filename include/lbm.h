@@ -121,6 +121,26 @@ int lbm_kinetic_y(lbm_ctx* ctx, const double* f, double* out2, lbm_stream stream
 int lbm_adjoint_step(lbm_ctx* ctx, const double* f_n, const double* lam_np1, double w,
                      double* lam_n, lbm_stream stream);
 
+/* Reverse-step variants (same role as the step variants). info4 = (R, G, W,
+ * PS): tiles of 64 x R cells, the 18 moving velocities split into G groups
+ * (one workgroup per tile and group), W the wavefronts-per-SIMD target, and
+ * PS = 1 when a per-cell pass first forms the equilibrium/objective terms
+ * and the rest plane (then the context's [4][ny][nx] buffer holds them).
+ * Every variant computes the same result up to rounding. */
+int lbm_adjoint_variant_count(void);
+int lbm_adjoint_variant_info(int32_t variant, int32_t* info4);
+int lbm_set_adjoint_variant(lbm_ctx* ctx, int32_t variant);
+int lbm_get_adjoint_variant(lbm_ctx* ctx, int32_t* variant);
+
+/* Autotuner of the reverse step: times lbm_adjoint_step(f_n, lam_np1 ->
+ * lam_tmp) for variants[0..nv) (nv = 0: all), one warm-up call then nsteps
+ * timed calls with HIP events on `stream`; ms_out: NULL or host
+ * double[nv or count] (ms per call). Leaves the fastest selected.
+ * Synchronous. */
+int lbm_tune_adjoint(lbm_ctx* ctx, const double* f_n, const double* lam_np1, double* lam_tmp,
+                     int32_t nsteps, const int32_t* variants, int32_t nv, double* ms_out,
+                     lbm_stream stream);
+
 /* Vector-Jacobian product of lbm_init: g_q = sum_i lam0_i d f_i^eq / d q for
  * q = rho, ux, uy, T per cell (Eq. (28) with Eqs. (44)-(46)). Inputs: the four
  * scalar fields lbm_init took and a 19-plane lam0; outputs: four scalar

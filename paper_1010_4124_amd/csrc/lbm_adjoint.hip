@@ -15,9 +15,12 @@
 // the objective gradient, and mu of the face between cells I and I+1 is
 // c (lambda'(I+1) - lambda'(I)).
 //
-// A one-wavefront workgroup owns a 64 x R tile. Phase 1 forms the K's of its
-// cells (19 values of f and of lambda' per cell) and writes the rest plane.
-// Phase 2 stages, per moving velocity, f_i with a 4-cell halo and lambda'_i
+// A one-wavefront workgroup owns a 64 x R tile and one of G groups of the 18
+// moving velocities. Phase 1 forms the K's of its cells (19 values of f and
+// of lambda' per cell) and group 0 writes the rest plane; in the state-pass
+// variants a per-cell kernel has formed the K's and the rest plane already
+// and phase 1 only reads them. Phase 2 stages, per moving velocity of the
+// group, f_i with a 4-cell halo and lambda'_i
 // with a 3-cell halo in LDS (lambda' is zero in ghost cells except on
 // periodic axes: ghosts have no update). Each lane recomputes the R+4 faces
 // whose stencils touch its R-cell strip and applies the reverse of the WENO
@@ -40,9 +43,10 @@ struct AdjArgs {
     const double* __restrict__ f;
     const double* __restrict__ lam1;
     double* __restrict__ lam0;
+    const double* __restrict__ kst;  // K0, Kx, Ky, KE planes (state-pass variants)
     int nx, ny;
     int bc[4];
-    int tiles_x, ntiles, per_xcd;
+    int tiles_x, nwork, per_xcd;
     double cx, cy, ct, wdxdy;  // w dx dy: weight of the objective term
     Consts k;
 };
@@ -166,8 +170,8 @@ __device__ __forceinline__ double wall_term(const AdjArgs& a, int j, int wx, int
     return vn * sum;
 }
 
-template <int R, bool BND>
-__device__ __forceinline__ void adj_planes(const AdjArgs& a, int x0, int y0, int lane,
+template <int R, int G, bool BND>
+__device__ __forceinline__ void adj_planes(const AdjArgs& a, int grp, int x0, int y0, int lane,
                                            const TileMapG& tf, const TileMapG& tl, double* s_f,
                                            double* s_l, double* s_ax, const double (&K0)[R],
                                            const double (&Kx)[R], const double (&Ky)[R],
@@ -184,8 +188,9 @@ __device__ __forceinline__ void adj_planes(const AdjArgs& a, int x0, int y0, int
     const bool wall_yhi = a.bc[YHI] == REFLECT && y0 + R > a.ny - HALO;
     const bool wall_xlo = a.bc[XLO] == REFLECT && x0 < HALO;
     const bool wall_xhi = a.bc[XHI] == REFLECT && x0 + ATX > a.nx - HALO;
+    const int i0 = 1 + grp * (18 / G), iend = i0 + 18 / G;
 #pragma unroll 1
-    for (int i = 1; i < NV; ++i) {
+    for (int i = i0; i < iend; ++i) {
         double pf[SF::NPRE], pl[SL::NPRE];
         stage_load_g<R, FH, AP, BND, false>(a.f, g, a.k, i, x0, y0, lane, tf, plane, pf);
         stage_load_g<R, LH, AP, BND, true>(a.lam1, g, a.k, i, x0, y0, lane, tl, plane, pl);
@@ -253,8 +258,80 @@ __device__ __forceinline__ void adj_planes(const AdjArgs& a, int x0, int y0, int
     }
 }
 
-template <int R>
-__global__ __launch_bounds__(64) void k_adjoint(AdjArgs a)
+// Per-cell terms of phase 1 for the cell whose plane-0 values sit at pf
+// (f^n) and pl (lambda^{n+1}), planes `plane` apart: the sums over i of
+// lambda'_i times the partials of f_i^eq through (rho, j, E), scaled by
+// dt/tau, plus the objective's gradient w dx dy (u_y v_iy - u_y^2/2).
+struct AdjCell {
+    double K0, Kx, Ky, KE, rest;  // rest: the rest particle's adjoint
+};
+
+__device__ __forceinline__ AdjCell adj_cell(const double* pf, const double* pl, int64_t plane,
+                                            const Consts& k, double ct, double wdxdy)
+{
+    double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const double fi = pf[i * plane];
+        r += fi;
+        jx = __builtin_fma(fi, k.vx[i], jx);
+        jy = __builtin_fma(fi, k.vy[i], jy);
+        E = __builtin_fma(fi, k.hv2[i], E);
+    }
+    const double ux = jx / r, uy = jy / r;
+    const double u2 = ux * ux + uy * uy;
+    const double T = E / r - 0.5 * u2;
+    const double iT = 1.0 / T;
+    const double t0 = 1.0 - u2 / (2.0 * T);
+    const double b = 1.0 - t0;
+    const double F1 = weight_c(k, 0, T), F2 = weight_c(k, 1, T), F3 = weight_c(k, 2, T);
+    const double F0 = 1.0 - 6.0 * (F1 + F2 + F3);
+    const double d1 = dweight_c(k, 0, T), d2 = dweight_c(k, 1, T), d3 = dweight_c(k, 2, T);
+    const double d0 = -6.0 * (d1 + d2 + d3);
+    // sums over i of lambda'_i times the partials of f_i^eq (Eq. (28)),
+    // with P = (1-b)(1+eta) + eta^2/2 + eta^3/6, eta = v.u / T
+    double sP = 0.0, sX = 0.0, sY = 0.0, sT = 0.0, l0 = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const double L = pl[i * plane];
+        if (i == 0) l0 = L;
+        // weight of the speed shell of velocity i and its T derivative
+        const double Fs = i == 0 ? F0 : i < 7 ? F1 : i < 13 ? F2 : F3;
+        const double dFs = i == 0 ? d0 : i < 7 ? d1 : i < 13 ? d2 : d3;
+        const double eta = __builtin_fma(k.vx[i], ux * iT, k.vy[i] * (uy * iT));
+        const double P = feq_poly(eta, t0);
+        const double Pxi = t0 + eta * (1.0 + 0.5 * eta);        // T dP/dxi
+        const double Pb = -(1.0 + eta);                          // dP/db
+        const double PTT = -eta * (t0 + eta * (1.0 + 0.5 * eta));  // T dP/dT at fixed xi, b
+        const double LF = L * Fs;
+        sP = __builtin_fma(LF, P, sP);
+        sX = __builtin_fma(LF, __builtin_fma(Pxi, k.vx[i], Pb * ux), sX);
+        sY = __builtin_fma(LF, __builtin_fma(Pxi, k.vy[i], Pb * uy), sY);
+        sT += L * __builtin_fma(dFs * T, P, Fs * (PTT - Pb * b));
+    }
+    // f^eq depends on (rho, ux, uy, T): d/drho = F P, d/du = rho F (Pxi v + Pb u)/T,
+    // d/dT = rho (F' P + F (PTT - Pb b) / T)
+    double rb = sP, uxb = r * iT * sX, uyb = r * iT * sY, Tb = r * iT * sT;
+    // T = E/rho - u^2/2, u = j/rho
+    const double Eb = Tb / r;
+    rb -= Tb * (E / (r * r));
+    const double uxb2 = uxb - Tb * ux, uyb2 = uyb - Tb * uy;
+    const double jxb = uxb2 / r, jyb = uyb2 / r;
+    rb -= (uxb2 * ux + uyb2 * uy) / r;
+    AdjCell c;
+    c.K0 = __builtin_fma(ct, rb, -0.5 * wdxdy * uy * uy);
+    c.Kx = ct * jxb;
+    c.Ky = __builtin_fma(ct, jyb, wdxdy * uy);
+    c.KE = ct * Eb;
+    // rest particle: no convection
+    c.rest = __builtin_fma(1.0 - ct, l0, c.K0);
+    return c;
+}
+
+// One (tile, group) work item of the reverse step. PS: the K's come from
+// a.kst (written with the rest plane by k_adj_state).
+template <int R, int G, int W, bool PS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_adjoint(AdjArgs a)
 {
     using SF = StageG<R, FH, AP>;
     using SL = StageG<R, LH, AP>;
@@ -263,8 +340,9 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a)
     __shared__ double s_ax[R * AXP];
 
     const int b = blockIdx.x;
-    const int tile = (b & 7) * a.per_xcd + (b >> 3);
-    if (tile >= a.ntiles) return;
+    const int work = (b & 7) * a.per_xcd + (b >> 3);
+    if (work >= a.nwork) return;
+    const int tile = work / G, grp = work - tile * G;
     const int lane = threadIdx.x;
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
     const int x0 = tx * ATX, y0 = ty * R;
@@ -281,76 +359,48 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a)
         const bool act = gx < a.nx && gy < a.ny;
         K0[m] = Kx[m] = Ky[m] = KE[m] = 0.0;
         if (!act) continue;
-        const double* pf = a.f + (int64_t)gy * a.nx + x0;
-        const double* pl = a.lam1 + (int64_t)gy * a.nx + x0;
-        double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            const double fi = (pf + i * plane)[(unsigned)lane];
-            r += fi;
-            jx = __builtin_fma(fi, a.k.vx[i], jx);
-            jy = __builtin_fma(fi, a.k.vy[i], jy);
-            E = __builtin_fma(fi, a.k.hv2[i], E);
+        const int64_t c = (int64_t)gy * a.nx + gx;
+        if (PS) {
+            K0[m] = a.kst[c];
+            Kx[m] = a.kst[plane + c];
+            Ky[m] = a.kst[2 * plane + c];
+            KE[m] = a.kst[3 * plane + c];
+        } else {
+            const AdjCell q = adj_cell(a.f + c, a.lam1 + c, plane, a.k, a.ct, a.wdxdy);
+            K0[m] = q.K0;
+            Kx[m] = q.Kx;
+            Ky[m] = q.Ky;
+            KE[m] = q.KE;
+            if (grp == 0) a.lam0[c] = q.rest;
         }
-        const double ux = jx / r, uy = jy / r;
-        const double u2 = ux * ux + uy * uy;
-        const double T = E / r - 0.5 * u2;
-        const double iT = 1.0 / T;
-        const double t0 = 1.0 - u2 / (2.0 * T);
-        const double b = 1.0 - t0;
-        double Fk[4], dF[4];
-        Fk[1] = weight_c(a.k, 0, T);
-        Fk[2] = weight_c(a.k, 1, T);
-        Fk[3] = weight_c(a.k, 2, T);
-        Fk[0] = 1.0 - 6.0 * (Fk[1] + Fk[2] + Fk[3]);
-        dF[1] = dweight_c(a.k, 0, T);
-        dF[2] = dweight_c(a.k, 1, T);
-        dF[3] = dweight_c(a.k, 2, T);
-        dF[0] = -6.0 * (dF[1] + dF[2] + dF[3]);
-        // sums over i of lambda'_i times the partials of f_i^eq (Eq. (28)),
-        // with P = (1-b)(1+eta) + eta^2/2 + eta^3/6, eta = v.u / T
-        double sP = 0.0, sX = 0.0, sY = 0.0, sT = 0.0, l0 = 0.0;
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            const double L = (pl + i * plane)[(unsigned)lane];
-            if (i == 0) l0 = L;
-            const int s = i == 0 ? 0 : 1 + (i - 1) / 6;
-            const double eta = __builtin_fma(a.k.vx[i], ux * iT, a.k.vy[i] * (uy * iT));
-            const double P = feq_poly(eta, t0);
-            const double Pxi = t0 + eta * (1.0 + 0.5 * eta);        // T dP/dxi
-            const double Pb = -(1.0 + eta);                          // dP/db
-            const double PTT = -eta * (t0 + eta * (1.0 + 0.5 * eta));  // T dP/dT at fixed xi, b
-            const double LF = L * Fk[s];
-            sP = __builtin_fma(LF, P, sP);
-            sX = __builtin_fma(LF, __builtin_fma(Pxi, a.k.vx[i], Pb * ux), sX);
-            sY = __builtin_fma(LF, __builtin_fma(Pxi, a.k.vy[i], Pb * uy), sY);
-            sT += L * __builtin_fma(dF[s] * T, P, Fk[s] * (PTT - Pb * b));
-        }
-        // f^eq depends on (rho, ux, uy, T): d/drho = F P, d/du = rho F (Pxi v + Pb u)/T,
-        // d/dT = rho (F' P + F (PTT - Pb b) / T)
-        double rb = sP, uxb = r * iT * sX, uyb = r * iT * sY, Tb = r * iT * sT;
-        // T = E/rho - u^2/2, u = j/rho
-        const double Eb = Tb / r;
-        rb -= Tb * (E / (r * r));
-        const double uxb2 = uxb - Tb * ux, uyb2 = uyb - Tb * uy;
-        const double jxb = uxb2 / r, jyb = uyb2 / r;
-        rb -= (uxb2 * ux + uyb2 * uy) / r;
-        K0[m] = __builtin_fma(a.ct, rb, -0.5 * a.wdxdy * uy * uy);
-        Kx[m] = a.ct * jxb;
-        Ky[m] = __builtin_fma(a.ct, jyb, a.wdxdy * uy);
-        KE[m] = a.ct * Eb;
-        // rest particle: no convection
-        (a.lam0 + (int64_t)gy * a.nx + x0)[(unsigned)lane] = __builtin_fma(1.0 - a.ct, l0, K0[m]);
     }
 
-    // ---- phase 2: the 18 moving velocities ----
+    // ---- phase 2: the group's moving velocities ----
     const GridBC g = grid_of(a);
     const TileMapG tf = tile_map_g<R, FH, false>(g, x0, y0, lane, !interior);
     const TileMapG tl = tile_map_g<R, LH, true>(g, x0, y0, lane, !interior);
     if (interior)
-        adj_planes<R, false>(a, x0, y0, lane, tf, tl, s_f, s_l, s_ax, K0, Kx, Ky, KE);
+        adj_planes<R, G, false>(a, grp, x0, y0, lane, tf, tl, s_f, s_l, s_ax, K0, Kx, Ky, KE);
     else
-        adj_planes<R, true>(a, x0, y0, lane, tf, tl, s_f, s_l, s_ax, K0, Kx, Ky, KE);
+        adj_planes<R, G, true>(a, grp, x0, y0, lane, tf, tl, s_f, s_l, s_ax, K0, Kx, Ky, KE);
+}
+
+// State pass of the reverse step, one thread per cell: the K's of phase 1
+// (to kst) and the rest particle's adjoint (to plane 0 of lam0).
+__global__ __launch_bounds__(256) void k_adj_state(const double* __restrict__ f,
+                                                   const double* __restrict__ lam1,
+                                                   double* __restrict__ lam0,
+                                                   double* __restrict__ kst, int64_t n, double ct,
+                                                   double wdxdy, Consts k)
+{
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= n) return;
+    const AdjCell q = adj_cell(f + c, lam1 + c, n, k, ct, wdxdy);
+    kst[c] = q.K0;
+    kst[n + c] = q.Kx;
+    kst[2 * n + c] = q.Ky;
+    kst[3 * n + c] = q.KE;
+    lam0[c] = q.rest;
 }
 
 // ---------------------------------------------------------------------------
@@ -429,28 +479,63 @@ __global__ __launch_bounds__(256) void k_rowdot(const double* __restrict__ A,
 }
 
 // ---------------------------------------------------------------------------
-constexpr int ADJ_R = 4;
+// Reverse-step variants: rows per lane R, velocity groups G, waves-per-SIMD
+// target W and whether a state pass forms the K's first (PS).
+struct AdjVariant {
+    int R, G, W, PS;
+    void (*kernel)(AdjArgs);
+};
 
-hipError_t launch_adjoint(const double* f, const double* lam1, double* lam0, const Consts& k,
-                          int nx, int ny, const int bc[4], double cx, double cy, double ct,
-                          double wdxdy, hipStream_t st)
+#define LBM_ADJ_VARIANT(R, G, W, PS) {R, G, W, PS, k_adjoint<R, G, W, PS>},
+// (multi-plane groups under the two-wave budget spill and are left out)
+static const AdjVariant kAdjVariants[] = {
+    LBM_ADJ_VARIANT(4, 1, 1, 0) LBM_ADJ_VARIANT(4, 3, 1, 0) LBM_ADJ_VARIANT(4, 6, 1, 0)
+    LBM_ADJ_VARIANT(4, 18, 1, 1) LBM_ADJ_VARIANT(4, 18, 2, 1) LBM_ADJ_VARIANT(2, 18, 2, 1)
+    LBM_ADJ_VARIANT(4, 6, 1, 1) LBM_ADJ_VARIANT(4, 3, 1, 1)
+};
+#undef LBM_ADJ_VARIANT
+constexpr int kNumAdjVariants = sizeof(kAdjVariants) / sizeof(kAdjVariants[0]);
+
+int adj_variant_count() { return kNumAdjVariants; }
+int adj_variant_desc(int v, int info[4])
 {
+    if (v < 0 || v >= kNumAdjVariants) return -1;
+    info[0] = kAdjVariants[v].R;
+    info[1] = kAdjVariants[v].G;
+    info[2] = kAdjVariants[v].W;
+    info[3] = kAdjVariants[v].PS;
+    return 0;
+}
+
+hipError_t launch_adjoint(int variant, const double* f, const double* lam1, double* lam0,
+                          double* kst, const Consts& k, int nx, int ny, const int bc[4], double cx,
+                          double cy, double ct, double wdxdy, hipStream_t st)
+{
+    const AdjVariant& V = kAdjVariants[variant];
     AdjArgs a;
     a.f = f;
     a.lam1 = lam1;
     a.lam0 = lam0;
+    a.kst = kst;
     a.nx = nx;
     a.ny = ny;
     for (int s = 0; s < 4; ++s) a.bc[s] = bc[s];
     a.tiles_x = (nx + ATX - 1) / ATX;
-    a.ntiles = a.tiles_x * ((ny + ADJ_R - 1) / ADJ_R);
-    a.per_xcd = (a.ntiles + 7) / 8;
+    a.nwork = a.tiles_x * ((ny + V.R - 1) / V.R) * V.G;
+    a.per_xcd = (a.nwork + 7) / 8;
     a.cx = cx;
     a.cy = cy;
     a.ct = ct;
     a.wdxdy = wdxdy;
     a.k = k;
-    hipLaunchKernelGGL(k_adjoint<ADJ_R>, dim3(8 * a.per_xcd), dim3(64), 0, st, a);
+    if (V.PS) {
+        const int64_t n = (int64_t)nx * ny;
+        hipLaunchKernelGGL(k_adj_state, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, f,
+                           lam1, lam0, kst, n, ct, wdxdy, k);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(V.kernel, dim3(8 * a.per_xcd), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

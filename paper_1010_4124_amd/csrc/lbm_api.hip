@@ -112,6 +112,7 @@ int lbm_create(const lbm_params* p, lbm_ctx** out)
     lbmi_fill_consts(p, &c->k);
     const size_t n = (size_t)p->nx * p->ny;
     c->variant = lbmi_default_variant(p->nx, p->ny);
+    c->adj_variant = lbmi_default_adj_variant((int64_t)p->nx * p->ny);
     int maxtiles = 0;
     for (int v = 0; v < step_variant_count(); ++v) {
         const int t = step_ntiles(v, p->nx, p->ny);
@@ -299,8 +300,9 @@ int lbm_adjoint_step(lbm_ctx* c, const double* f_n, const double* lam_np1, doubl
     const size_t fb = NV * (size_t)p.nx * p.ny * sizeof(double);
     if (overlaps(lam_n, fb, lam_np1, fb) || overlaps(lam_n, fb, f_n, fb))
         return fail(LBM_EINVAL, "lam_n overlaps an input%s%lld");
-    hipError_t e = launch_adjoint(f_n, lam_np1, lam_n, c->k, p.nx, p.ny, p.bc, p.dt / p.dx,
-                                  p.dt / p.dy, p.dt / p.tau, w * p.dx * p.dy, (hipStream_t)stream);
+    hipError_t e = launch_adjoint(c->adj_variant, f_n, lam_np1, lam_n, c->msum, c->k, p.nx, p.ny,
+                                  p.bc, p.dt / p.dx, p.dt / p.dy, p.dt / p.tau, w * p.dx * p.dy,
+                                  (hipStream_t)stream);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_adjoint_step");
 }
 
@@ -377,6 +379,91 @@ int lbm_tune_step(lbm_ctx* c, const double* f_in, double* f_tmp, int32_t nsteps,
         }
     }
     c->variant = rc == LBM_OK ? best : keep;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return rc;
+}
+
+// Default reverse-step variant: one velocity per workgroup after a state
+// pass, so that small grids still fill the chip.
+int lbmi_default_adj_variant(int64_t cells)
+{
+    (void)cells;
+    for (int v = 0; v < adj_variant_count(); ++v) {
+        int d[4];
+        adj_variant_desc(v, d);
+        if (d[0] == 4 && d[1] == 18 && d[2] == 2 && d[3] == 1) return v;
+    }
+    return 0;
+}
+
+int lbm_adjoint_variant_count(void) { return adj_variant_count(); }
+
+int lbm_adjoint_variant_info(int32_t v, int32_t* info4)
+{
+    int d[4];
+    if (!info4 || adj_variant_desc(v, d)) return fail(LBM_EINVAL, "bad adjoint variant%s%lld");
+    for (int j = 0; j < 4; ++j) info4[j] = d[j];
+    return LBM_OK;
+}
+
+int lbm_set_adjoint_variant(lbm_ctx* c, int32_t v)
+{
+    if (!c || v < 0 || v >= adj_variant_count())
+        return fail(LBM_EINVAL, "bad adjoint variant%s%lld");
+    c->adj_variant = v;
+    return LBM_OK;
+}
+
+int lbm_get_adjoint_variant(lbm_ctx* c, int32_t* v)
+{
+    if (!c || !v) return fail(LBM_EINVAL, "null argument%s%lld");
+    *v = c->adj_variant;
+    return LBM_OK;
+}
+
+int lbm_tune_adjoint(lbm_ctx* c, const double* f_n, const double* lam_np1, double* lam_tmp,
+                     int32_t nsteps, const int32_t* variants, int32_t nv, double* ms_out,
+                     lbm_stream stream)
+{
+    if (!c || !f_n || !lam_np1 || !lam_tmp || nsteps < 1 || nv < 0 || (nv > 0 && !variants))
+        return fail(LBM_EINVAL, "bad argument%s%lld");
+    const int count = nv > 0 ? nv : adj_variant_count();
+    for (int j = 0; j < count; ++j) {
+        const int v = nv > 0 ? variants[j] : j;
+        if (v < 0 || v >= adj_variant_count()) return fail(LBM_EINVAL, "bad adjoint variant%s%lld");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return hip_fail(e, "lbm_tune_adjoint");
+    }
+    const int keep = c->adj_variant;
+    int best = keep, rc = LBM_OK;
+    double best_ms = 0.0;
+    for (int j = 0; j < count && rc == LBM_OK; ++j) {
+        c->adj_variant = nv > 0 ? variants[j] : j;
+        float ms = 0.f;
+        if ((rc = lbm_adjoint_step(c, f_n, lam_np1, 1.0, lam_tmp, stream)) != LBM_OK) break;
+        if ((e = hipEventRecord(e0, st)) != hipSuccess) { rc = hip_fail(e, "tune"); break; }
+        for (int s = 0; s < nsteps && rc == LBM_OK; ++s)
+            rc = lbm_adjoint_step(c, f_n, lam_np1, 1.0, lam_tmp, stream);
+        if (rc != LBM_OK) break;
+        if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+            (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+            rc = hip_fail(e, "tune");
+            break;
+        }
+        const double per = ms / nsteps;
+        if (ms_out) ms_out[j] = per;
+        if (j == 0 || per < best_ms) {
+            best_ms = per;
+            best = c->adj_variant;
+        }
+    }
+    c->adj_variant = rc == LBM_OK ? best : keep;
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     return rc;

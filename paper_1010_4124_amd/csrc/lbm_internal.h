@@ -12,6 +12,7 @@ struct lbm_ctx {
     lbm_params p;
     int device = 0;
     int variant = 0;
+    int adj_variant = 0;
     int ke_cap = 0;
     lbmd::Consts k;                // per-context constants (kernel arguments)
     double* scratch = nullptr;     // 19 planes: ping-pong state of multi-step calls
@@ -24,6 +25,7 @@ int lbmi_validate(const lbm_params* p);
 void lbmi_fill_consts(const lbm_params* p, lbmd::Consts* h);
 int lbmi_default_variant(int nx, int ny);
 int lbmi_default_variant_cells(int64_t cells);
+int lbmi_default_adj_variant(int64_t cells);
 void lbmi_set_error(const char* msg);
 
 namespace lbmd {
@@ -45,9 +47,11 @@ hipError_t launch_moments(const double* f, double* rho, double* ux, double* uy, 
                           const Consts& k, int64_t n, hipStream_t st);
 hipError_t launch_kinetic_part(const double* f, const Consts& k, int64_t n, double* part,
                                int* nparts, hipStream_t st);
-hipError_t launch_adjoint(const double* f, const double* lam1, double* lam0, const Consts& k,
-                          int nx, int ny, const int bc[4], double cx, double cy, double ct,
-                          double wdxdy, hipStream_t st);
+int adj_variant_count();
+int adj_variant_desc(int v, int info[4]);
+hipError_t launch_adjoint(int variant, const double* f, const double* lam1, double* lam0,
+                          double* kst, const Consts& k, int nx, int ny, const int bc[4], double cx,
+                          double cy, double ct, double wdxdy, hipStream_t st);
 hipError_t launch_init_vjp(const double* rho, const double* ux, const double* uy, const double* T,
                            const double* lam, double* grho, double* gux, double* guy, double* gT,
                            const Consts& k, int64_t n, hipStream_t st);

@@ -105,6 +105,12 @@ def lib():
         "lbm_batch_set_schedule": (C.c_int, [_P, _I, _I]),
         "lbm_batch_get_schedule": (C.c_int, [_P, C.POINTER(_I)]),
         "lbm_tune_step": (C.c_int, [_P, _P, _P, _I, C.POINTER(_I), _I, C.POINTER(C.c_double), _P]),
+        "lbm_adjoint_variant_count": (C.c_int, []),
+        "lbm_adjoint_variant_info": (C.c_int, [_I, C.POINTER(_I)]),
+        "lbm_set_adjoint_variant": (C.c_int, [_P, _I]),
+        "lbm_get_adjoint_variant": (C.c_int, [_P, C.POINTER(_I)]),
+        "lbm_tune_adjoint": (C.c_int, [_P, _P, _P, _P, _I, C.POINTER(_I), _I,
+                                       C.POINTER(C.c_double), _P]),
         "lbm_batch_tune": (C.c_int, [_P, _P, _P, _I, C.POINTER(_I), _I, C.POINTER(_I), _I,
                                      C.POINTER(C.c_double), _P]),
         "lbm_last_error": (C.c_char_p, []),
@@ -226,6 +232,39 @@ def lbm_get_step_variant(h):
     v = _I()
     _check(lib().lbm_get_step_variant(h, C.byref(v)))
     return v.value
+
+
+def lbm_adjoint_variant_count():
+    return int(lib().lbm_adjoint_variant_count())
+
+
+def lbm_adjoint_variant_info(v):
+    """(rows per lane R, velocity groups G, waves-per-SIMD target W, state pass PS)."""
+    info = (_I * 4)()
+    _check(lib().lbm_adjoint_variant_info(int(v), info))
+    return tuple(int(x) for x in info)
+
+
+def lbm_set_adjoint_variant(h, v):
+    _check(lib().lbm_set_adjoint_variant(h, int(v)))
+
+
+def lbm_get_adjoint_variant(h):
+    v = _I()
+    _check(lib().lbm_get_adjoint_variant(h, C.byref(v)))
+    return v.value
+
+
+def lbm_tune_adjoint(h, nx, ny, f_n, lam_np1, lam_tmp, nsteps=5, variants=None, stream=None):
+    """Times the reverse-step variants; returns {variant: ms per call} and
+    leaves the fastest selected."""
+    vs = list(range(lbm_adjoint_variant_count())) if variants is None else [int(v) for v in variants]
+    ms = (C.c_double * len(vs))()
+    s = (NV, ny, nx)
+    _check(lib().lbm_tune_adjoint(h, _ptr(f_n, s, "f_n"), _ptr(lam_np1, s, "lam_np1"),
+                                  _ptr(lam_tmp, s, "lam_tmp"), int(nsteps), (_I * len(vs))(*vs),
+                                  len(vs), ms, _stream(stream)))
+    return {v: ms[j] for j, v in enumerate(vs)}
 
 
 def lbm_tune_step(h, nx, ny, f_in, f_tmp, nsteps=20, variants=None, stream=None):
@@ -505,3 +544,11 @@ class Context:
     @variant.setter
     def variant(self, v):
         lbm_set_step_variant(self.handle, v)
+
+    @property
+    def adj_variant(self):
+        return lbm_get_adjoint_variant(self.handle)
+
+    @adj_variant.setter
+    def adj_variant(self, v):
+        lbm_set_adjoint_variant(self.handle, v)

@@ -122,3 +122,28 @@ def tune_batch(b, f, nsteps=None, slots=(0,), reps=2, use_cache=True):
         db[key] = rec
         _store(db)
     return dict(rec, cached=False)
+
+
+def tune_adjoint(ctx, f, lam, nsteps=None, reps=2, use_cache=True):
+    """Select the fastest reverse-step variant for ctx (f, lam: representative
+    f^n and lambda^{n+1}); same repetition and tie rule as tune_context."""
+    key = context_key(ctx) + "|adjoint"
+    db = _load() if use_cache else {}
+    n = lbm.lbm_adjoint_variant_count()
+    if key in db and 0 <= db[key]["variant"] < n:
+        ctx.adj_variant = db[key]["variant"]
+        return dict(db[key], cached=True)
+    tmp = ctx.empty_f()
+    if nsteps is None:
+        nsteps = max(2, min(100, int(2e7 / (ctx.nx * ctx.ny))))
+    ms = {}
+    for _ in range(max(1, reps)):
+        for k, v in lbm.lbm_tune_adjoint(ctx.handle, ctx.nx, ctx.ny, f, lam, tmp, nsteps).items():
+            ms[k] = min(ms.get(k, v), v)
+    ctx.adj_variant = _pick(ms)
+    rec = {"variant": ctx.adj_variant, "ms": {str(k): v for k, v in ms.items()}}
+    if use_cache:
+        db = _load()
+        db[key] = rec
+        _store(db)
+    return dict(rec, cached=False)

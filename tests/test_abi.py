@@ -30,6 +30,13 @@ def test_version_and_variants_without_gpu():
         assert NT in (0, 1) and M in (0, 1, 2) and 18 % G == 0
     with pytest.raises(lbm.LbmError):
         lbm.lbm_step_variant_info(n)
+    na = lbm.lbm_adjoint_variant_count()
+    assert na >= 2
+    for v in range(na):
+        R, G, W, PS = lbm.lbm_adjoint_variant_info(v)
+        assert R in (2, 4, 8) and 18 % G == 0 and W >= 1 and PS in (0, 1)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_adjoint_variant_info(na)
 
 
 def test_create_rejects_bad_params_without_gpu():

@@ -46,12 +46,15 @@ def test_adjoint_step_parity(shape, bc):
     ref = oracle.adjoint_step(p, f, lam, 0.7)
     ctx = lbm.Context(nx, ny, 2e-2, 2.5e-2, 4e-4, 6e-4, bc, side_state=SIDES)
     fg, lg = torch.from_numpy(f).cuda(), torch.from_numpy(lam).cuda()
-    got = ctx.adjoint_step(fg, lg, 0.7)
-    err = nrel(got.cpu().numpy(), ref)
-    print(f"adjoint {shape} {bc}: {err:.2e}", flush=True)
-    assert err < TOL
-    again = ctx.adjoint_step(fg, lg, 0.7)
-    assert torch.equal(got, again)
+    for v in range(lbm.lbm_adjoint_variant_count()):
+        ctx.adj_variant = v
+        got = ctx.adjoint_step(fg, lg, 0.7)
+        err = nrel(got.cpu().numpy(), ref)
+        print(f"adjoint {shape} {bc} variant {lbm.lbm_adjoint_variant_info(v)}: {err:.2e}",
+              flush=True)
+        assert err < TOL, (v, err)
+        again = ctx.adjoint_step(fg, lg, 0.7)
+        assert torch.equal(got, again)
 
 
 def test_adjoint_objective_term_only():

@@ -57,3 +57,20 @@ def test_tune_batch_selects_pair():
     assert float((got - ref).abs().max() / ref.abs().max()) < 1e-14
     r2 = tune.tune_batch(b, f0)
     assert r2["cached"]
+
+
+def test_tune_adjoint_selects_fastest():
+    s = inputs.khi(128, 96, Dv=0.02, Drho=0.02, pert=1e-2)
+    ctx = lbm.Context.from_setup(s)
+    f0 = ctx.init(*s.fields())
+    lam = torch.randn_like(f0)
+    ref = ctx.adjoint_step(f0, lam, 1e-5)
+    r = tune.tune_adjoint(ctx, f0, lam, nsteps=2)
+    n = lbm.lbm_adjoint_variant_count()
+    assert len(r["ms"]) == n and all(v > 0 for v in r["ms"].values())
+    best = min(r["ms"].values())
+    ties = [int(k) for k, v in r["ms"].items() if v <= best * (1 + tune.TIE)]
+    assert ctx.adj_variant == min(ties)
+    got = ctx.adjoint_step(f0, lam, 1e-5)
+    assert float((got - ref).abs().max() / ref.abs().max()) < 1e-13
+    assert tune.tune_adjoint(ctx, f0, lam)["cached"]
