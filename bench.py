@@ -100,10 +100,12 @@ def read_traffic(kernel_name):
 
 
 def step_kernel_name(variant):
+    """The step's kernel(s): a state-pass variant (M = 2) launches k_state and
+    then the step kernel each step; both count as the step."""
     from paper_1010_4124_amd import lbm
     R, G, W, D, NT, M = lbm.lbm_step_variant_info(variant)
-    b = lambda x: "true" if x else "false"
-    return f"lbmd::k_step<{R}, {G}, {W}, {D}, {b(NT)}, {b(M)}>"
+    name = f"lbmd::k_step<{R}, {G}, {W}, {D}, {'true' if NT else 'false'}, {M}>"
+    return name + " + lbmd::k_state" if M == 2 else name
 
 
 # ---------------------------------------------------------------------------
@@ -151,9 +153,22 @@ def bench_forward_large(args):
     return r
 
 
+def tune_problem(prob):
+    """Tune the forward and reverse step variants of a gradient problem on
+    its own initial state (outside any timed region)."""
+    import torch
+    from paper_1010_4124_amd import inputs, tune
+    s = prob.fields(0.02, 0.02, inputs.mode_amplitudes(prob.nx, seed=7))
+    f0 = prob.ctx.init(*s.fields())
+    tune.tune_context(prob.ctx, f0, use_cache=False)
+    lam = torch.randn_like(f0)
+    tune.tune_adjoint(prob.ctx, f0, lam, use_cache=False)
+    del f0, lam
+
+
 def bench_adjoint(args):
     import torch
-    from paper_1010_4124_amd import inputs, lbm, objective
+    from paper_1010_4124_amd import inputs, lbm, objective, tune
     res = {}
     # reverse step alone at 256^2 and 2048^2
     for n, steps in ((256, 200), (2048, 20)):
@@ -161,6 +176,7 @@ def bench_adjoint(args):
         ctx = lbm.Context.from_setup(s)
         f0 = ctx.init(*s.fields())
         lam = [torch.zeros_like(f0), ctx.empty_f()]
+        tune.tune_adjoint(ctx, f0, torch.randn_like(f0), use_cache=False)
 
         def run():
             for q in range(steps):
@@ -169,6 +185,7 @@ def bench_adjoint(args):
         secs, _ = sync_time(run)
         mlups = n * n * steps / secs / 1e6
         res[f"reverse_step_{n}"] = {"MLUPS": mlups,
+                                    "variant": list(lbm.lbm_adjoint_variant_info(ctx.adj_variant)),
                                     "hbm_frac": mlups * 1e6 * ADJ_BYTES_PER_LUP / 1e9 / HBM_PEAK_GBS}
         del ctx, f0, lam
         torch.cuda.empty_cache()
@@ -177,6 +194,7 @@ def bench_adjoint(args):
     prob = objective.KHIProblem(256, 256, nsteps=args.adj_steps,
                                 window=(args.adj_steps // 2, args.adj_steps),
                                 schedule=objective.Schedule.every(200))
+    tune_problem(prob)
     fwd_secs, _ = sync_time(lambda: prob.run(0.02, 0.02, rng_amps))
     J, ck = prob.run(0.02, 0.02, rng_amps)
     grad_secs, _ = sync_time(lambda: prob.gradient(0.02, 0.02, rng_amps, ck=ck))
@@ -189,6 +207,7 @@ def bench_adjoint(args):
     n2 = args.adj_large_steps
     prob2 = objective.KHIProblem(2048, 2048, nsteps=n2, window=(n2 // 2, n2),
                                  schedule=objective.Schedule.sqrt(n2))
+    tune_problem(prob2)
     amps2 = inputs.mode_amplitudes(2048, seed=7)
     fsecs, _ = sync_time(lambda: prob2.run(0.01, 0.04, amps2, keep_checkpoints=False))
     J2, ck2 = prob2.run(0.01, 0.04, amps2)
@@ -294,24 +313,37 @@ def summarize(args):
         raise SystemExit(f"no step kernel in {trace}")
     # the tuner launches every variant a few times; the timed one dominates
     top = max(step, key=lambda r: int(r["Calls"]))
-    name = re.sub(r"^void ", "", top["Name"]).split("(")[0]
+    base = re.sub(r"^void ", "", top["Name"]).split("(")[0]
     avg_ns = float(top["AverageNs"])
+    parts = [base]
+    if base.endswith(", 2>"):
+        st = [r for r in stats if r["Name"].startswith("lbmd::k_state(")]
+        if not st:
+            raise SystemExit("state-pass variant without k_state in the trace")
+        avg_ns += float(st[0]["AverageNs"])
+        parts.append("lbmd::k_state")
+    name = " + ".join(parts)
 
     def per_dispatch(root, counter):
         rows = _rows(os.path.join(root, "**", "*counter_collection.csv"))
         by = {}
         for r in rows:
-            if "k_step<" in r["Kernel_Name"] and r["Counter_Name"] == counter:
+            if ("k_step<" in r["Kernel_Name"] or r["Kernel_Name"].startswith("lbmd::k_state(")) \
+                    and r["Counter_Name"] == counter:
                 k = re.sub(r"^void ", "", r["Kernel_Name"]).split("(")[0]
                 by.setdefault(k, []).append(float(r["Counter_Value"]))
         cp = [(int(r["Grid_Size"]), float(r["Counter_Value"])) for r in rows
               if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == counter]
-        if not by or not cp:
+        steps = {k: v for k, v in by.items() if "k_step<" in k}
+        if not steps or not cp:
             raise SystemExit(f"{counter}: step or copy dispatches missing in {root}")
-        k = max(by, key=lambda q: len(by[q]))
-        if k != name:
-            raise SystemExit(f"{counter}: counted {k}, traced {name}")
-        return statistics.mean(by[k]), max(cp)[1]
+        k = max(steps, key=lambda q: len(steps[q]))
+        if k != base:
+            raise SystemExit(f"{counter}: counted {k}, traced {base}")
+        total = statistics.mean(by[k])
+        if len(parts) > 1:
+            total += statistics.mean(by["lbmd::k_state"])
+        return total, max(cp)[1]
 
     f_k, f_c = per_dispatch(fetch, "FETCH_SIZE")
     w_k, w_c = per_dispatch(write, "WRITE_SIZE")
@@ -320,11 +352,11 @@ def summarize(args):
     cells = 512 * 512
     algo = BYTES_PER_LUP * cells
     lines = [
-        "# Step kernel, 512 x 512 shear layer: duration and HBM traffic",
+        "# Step kernel(s), 512 x 512 shear layer: duration and HBM traffic per step",
         "",
         f"kernel: {name}",
         f"source_sha1: {source_hash()}",
-        f"avg_duration_ns: {avg_ns:.1f}",
+        f"avg_duration_ns: {avg_ns:.1f} (per step, all of its kernels)",
         f"calls: {top['Calls']}",
         f"fetch_kib_per_dispatch: {f_k:.1f}",
         f"write_kib_per_dispatch: {w_k:.1f}",

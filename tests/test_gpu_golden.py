@@ -20,7 +20,7 @@ import numpy as np
 import pytest
 import torch
 
-from paper_1010_4124_amd import inputs, lbm
+from paper_1010_4124_amd import inputs, lbm, tune
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "khi512_oracle.npz")
@@ -44,6 +44,9 @@ def test_khi512_full_run_matches_oracle(gold):
     s = inputs.khi(512, 512, dx=1e-3, dy=1e-3, dt=1e-5, tau=1e-5, Dv=0.02, Drho=0.02)
     ctx = lbm.Context.from_setup(s)
     f = ctx.init(*s.fields())
+    # the variant the benchmark times: chosen by the same tuner
+    tune.tune_context(ctx, f, use_cache=False)
+    print(f"variant {lbm.lbm_step_variant_info(ctx.variant)}", flush=True)
     every = int(gold["ke_every"])
     checks = [int(c) for c in gold["checkpoints"]]
     ke = []
