@@ -56,7 +56,10 @@ enum {
                             interior cell m of the mirrored velocity (the
                             paper has no walls; this is the shear-layer setup) */
     LBM_BC_OUTFLOW = 3   /* zeroth-order extrapolation, Sec. IV.A, Eqs. (63)-(64):
-                            not implemented on the GPU (LBM_EUNSUPPORTED) */
+                            the three ghost layers hold f^eq of the moments
+                            of the nearest interior cell at the current time
+                            (forward calls only: lbm_adjoint_step returns
+                            LBM_EUNSUPPORTED) */
 };
 
 enum { LBM_XLO = 0, LBM_XHI = 1, LBM_YLO = 2, LBM_YHI = 3 };
@@ -68,6 +71,10 @@ typedef struct {
     double vk[3];              /* particle speeds, distinct and > 0; the paper uses 1, 2, 3 */
     double weno_eps;           /* WENO regulariser, 1e-6 in Eq. (52); > 0 */
     double side_state[4][4];   /* (rho, ux, uy, T) of each LBM_BC_FIXED_EQ side */
+    int32_t ke_axis;           /* velocity component u_n of the kinetic-energy
+                                  diagnostics rho u_n^2 / 2: 0 = u_y, 1 = u_x
+                                  (the interface normal; Sec. IV uses u_x) */
+    int32_t reserved;          /* must be 0 */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -94,9 +101,9 @@ int lbm_init(lbm_ctx* ctx, const double* rho, const double* ux, const double* uy
  * velocity along x and y and the BGK relaxation.
  * ke_log: NULL, or device double[2*nsteps] receiving for each step n the
  * transverse kinetic energy of the state the step starts from,
- * ke_log[2n] = sum_cells rho u_y^2 / 2 * dx * dy and ke_log[2n+1] =
- * max_cells rho u_y^2 / 2 (the Sec. IV growth diagnostic with the interface
- * normal along y). */
+ * ke_log[2n] = sum_cells rho u_n^2 / 2 * dx * dy and ke_log[2n+1] =
+ * max_cells rho u_n^2 / 2, u_n the velocity component that ke_axis names
+ * (the Sec. IV growth diagnostic, u_n normal to the interface). */
 int lbm_step(lbm_ctx* ctx, const double* f_in, double* f_out, int32_t nsteps,
              double* ke_log, lbm_stream stream);
 
@@ -105,13 +112,16 @@ int lbm_step(lbm_ctx* ctx, const double* f_in, double* f_out, int32_t nsteps,
 int lbm_moments(lbm_ctx* ctx, const double* f, double* rho, double* ux, double* uy,
                 double* T, lbm_stream stream);
 
-/* out2[0] = sum_cells rho u_y^2 / 2 * dx * dy, out2[1] = max_cells
- * rho u_y^2 / 2 of f (device double[2]). */
+/* out2[0] = sum_cells rho u_n^2 / 2 * dx * dy, out2[1] = max_cells
+ * rho u_n^2 / 2 of f (device double[2]); u_n is u_y, or u_x when
+ * ke_axis = 1 (as in every energy log below). */
 int lbm_kinetic_y(lbm_ctx* ctx, const double* f, double* out2, lbm_stream stream);
 
 /* Discrete adjoint of one step (reverse mode of lbm_step with nsteps = 1):
  *   lam_n = (dS/df)^T lam_np1 + w dE_y/df,   S = the step of Eq. (47),
- * evaluated at f = f_n, with E_y = sum_cells rho u_y^2 / 2 * dx * dy. The
+ * evaluated at f = f_n, with E_y = sum_cells rho u_y^2 / 2 * dx * dy (the
+ * objective is E_y: ke_axis must be 0, and outflow sides are not supported:
+ * LBM_EUNSUPPORTED). The
  * transpose covers the WENO5 fluxes including their nonlinear weights
  * (Eqs. (48)-(55)), the equilibrium through the moments (Eqs. (10), (28),
  * (44)-(46)), the BGK term and the ghost layers (periodic images, mirrored

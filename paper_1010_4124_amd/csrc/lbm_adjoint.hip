@@ -53,7 +53,8 @@ struct AdjArgs {
 
 __device__ __forceinline__ GridBC grid_of(const AdjArgs& a)
 {
-    return GridBC{a.nx, a.ny, {a.bc[0], a.bc[1], a.bc[2], a.bc[3]}};
+    return GridBC{a.nx, a.ny, {a.bc[0], a.bc[1], a.bc[2], a.bc[3]},
+                  {nullptr, nullptr, nullptr, nullptr}};
 }
 
 __device__ __forceinline__ double dweight_c(const Consts& k, int s, double T)

@@ -52,14 +52,14 @@ int lbmi_validate(const lbm_params* p)
         return fail(LBM_EINVAL, "vk must be distinct%s%lld");
     for (int s = 0; s < 4; ++s) {
         if (p->bc[s] < 0 || p->bc[s] > 3) return fail(LBM_EINVAL, "unknown boundary code%s%lld");
-        if (p->bc[s] == LBM_BC_OUTFLOW)
-            return fail(LBM_EUNSUPPORTED, "outflow boundaries are not implemented%s%lld");
         const int n = s < 2 ? p->nx : p->ny;
         if (p->bc[s] != LBM_BC_PERIODIC && n < HALO)
             return fail(LBM_EINVAL, "a non-periodic axis needs at least 3 cells%s%lld");
         if (p->bc[s] == LBM_BC_FIXED_EQ && (!(p->side_state[s][0] > 0) || !(p->side_state[s][3] > 0)))
             return fail(LBM_EINVAL, "fixed-equilibrium side needs rho > 0 and T > 0%s%lld");
     }
+    if (p->ke_axis != 0 && p->ke_axis != 1) return fail(LBM_EINVAL, "ke_axis must be 0 or 1%s%lld");
+    if (p->reserved != 0) return fail(LBM_EINVAL, "reserved must be 0%s%lld");
     if ((p->bc[0] == LBM_BC_PERIODIC) != (p->bc[1] == LBM_BC_PERIODIC) ||
         (p->bc[2] == LBM_BC_PERIODIC) != (p->bc[3] == LBM_BC_PERIODIC))
         return fail(LBM_EINVAL, "periodic must be set on both sides of an axis%s%lld");
@@ -124,10 +124,20 @@ int lbm_create(const lbm_params* p, lbm_ctx** out)
     if ((e = hipMalloc(&c->scratch, NV * n * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&c->ke_part, 2 * (size_t)c->ke_cap * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&c->colbuf, (size_t)p->nx * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&c->msum, 8 * n * sizeof(double))) != hipSuccess) {
+        (e = hipMalloc(&c->msum, 8 * n * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&c->gbuf, NV * 2 * ((size_t)p->nx + p->ny) * sizeof(double))) !=
+            hipSuccess) {
         lbm_destroy(c);
         g_err = std::string("hipMalloc: ") + hipGetErrorString(e);
         return LBM_ENOMEM;
+    }
+    {
+        size_t o = 0;
+        for (int sd = 0; sd < 4; ++sd) {
+            const size_t len = sd < 2 ? (size_t)p->ny : (size_t)p->nx;
+            c->gb[sd] = p->bc[sd] == LBM_BC_OUTFLOW ? c->gbuf + o : nullptr;
+            o += NV * len;
+        }
     }
     // f^eq of the fixed sides, evaluated on the device by the same
     // equilibrium code as every other cell, then kept in the constants
@@ -150,6 +160,7 @@ void lbm_destroy(lbm_ctx* c)
     if (c->ke_part) hipFree(c->ke_part);
     if (c->colbuf) hipFree(c->colbuf);
     if (c->msum) hipFree(c->msum);
+    if (c->gbuf) hipFree(c->gbuf);
     delete c;
 }
 
@@ -203,19 +214,24 @@ int lbm_step(lbm_ctx* c, const double* f_in, double* f_out, int32_t nsteps, doub
         const double* m_in = nullptr;
         double* m_out = nullptr;
         int nparts = ntiles;
+        if (c->gb[0] || c->gb[1] || c->gb[2] || c->gb[3]) {
+            // outflow ghosts of the state this step starts from
+            hipError_t e = launch_outflow(src, p.nx, p.ny, c->gb, c->k, st);
+            if (e != hipSuccess) return hip_fail(e, "lbm_step outflow");
+        }
         if (mode == 1) {
             m_in = c->msum + 4 * n * (s % 2);
             m_out = c->msum + 4 * n * ((s + 1) % 2);
         } else if (mode == 2) {
             // state pass: cell state, rest particle and energy partials
-            hipError_t e = launch_state(src, dst, c->msum, n, ct, ke_log ? c->ke_part : nullptr,
-                                        &nparts, c->k, st);
+            hipError_t e = launch_state(src, dst, c->msum, n, ct, p.ke_axis,
+                                        ke_log ? c->ke_part : nullptr, &nparts, c->k, st);
             if (e != hipSuccess) return hip_fail(e, "lbm_step state");
             m_in = c->msum;
         }
         hipError_t e = launch_step(c->variant, src, dst, c->k,
                                    ke_log && mode != 2 ? c->ke_part : nullptr, p.nx, p.ny, p.bc,
-                                   cx, cy, ct, m_in, m_out, st);
+                                   cx, cy, ct, p.ke_axis, c->gb, m_in, m_out, st);
         if (e != hipSuccess) return hip_fail(e, "lbm_step");
         if (ke_log) {
             e = launch_reduce_pairs(c->ke_part, nparts, p.dx * p.dy, ke_log + 2 * s, st);
@@ -244,7 +260,7 @@ int lbm_kinetic_y(lbm_ctx* c, const double* f, double* out2, lbm_stream stream)
     const int64_t n = (int64_t)c->p.nx * c->p.ny;
     int np = 0;
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = launch_kinetic_part(f, c->k, n, c->ke_part, &np, st);
+    hipError_t e = launch_kinetic_part(f, c->k, n, c->p.ke_axis, c->ke_part, &np, st);
     if (e == hipSuccess) e = launch_reduce_pairs(c->ke_part, np, c->p.dx * c->p.dy, out2, st);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_kinetic_y");
 }
@@ -299,6 +315,11 @@ int lbm_adjoint_step(lbm_ctx* c, const double* f_n, const double* lam_np1, doubl
 {
     if (!c || !f_n || !lam_np1 || !lam_n) return fail(LBM_EINVAL, "null argument%s%lld");
     const lbm_params& p = c->p;
+    for (int sd = 0; sd < 4; ++sd)
+        if (p.bc[sd] == LBM_BC_OUTFLOW)
+            return fail(LBM_EUNSUPPORTED, "the reverse step has no outflow sides%s%lld");
+    if (p.ke_axis != 0)
+        return fail(LBM_EUNSUPPORTED, "the reverse step's objective is E_y (ke_axis 0)%s%lld");
     const size_t fb = NV * (size_t)p.nx * p.ny * sizeof(double);
     if (overlaps(lam_n, fb, lam_np1, fb) || overlaps(lam_n, fb, f_n, fb))
         return fail(LBM_EINVAL, "lam_n overlaps an input%s%lld");

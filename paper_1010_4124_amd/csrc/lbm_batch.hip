@@ -35,7 +35,9 @@ namespace lbmd {
 struct BatchInst {
     int64_t off;     // element offset of the instance's [19][ny][nx] block
     int64_t moff;    // element offset of its [4][ny][nx] moment sums
+    int64_t goff[4]; // element offsets of its outflow ghost arrays, or -1
     int nx, ny;
+    int ke_axis;
     int bc[4];
     int tiles_x;
     int ntiles;      // tiles of the current variant
@@ -51,6 +53,7 @@ struct BatchArgs {
     const double* __restrict__ fin;
     double* __restrict__ fout;
     double* __restrict__ ke_part;          // [sum of ntiles][2] or null
+    const double* gbuf;                    // outflow ghost arrays of all instances
     const BatchInst* __restrict__ inst;
     const int2* __restrict__ work;         // item -> (instance, tile x groups or tile)
     const double* __restrict__ m_in;       // carried moment sums (M variants)
@@ -81,6 +84,9 @@ void k_step_batch(BatchArgs a)
         s.bc[2] = d.bc[2];
         s.bc[3] = d.bc[3];
         s.tiles_x = d.tiles_x;
+        s.ke_axis = d.ke_axis;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s.gb[q] = d.goff[q] >= 0 ? a.gbuf + d.goff[q] : nullptr;
         s.cx = d.cx;
         s.cy = d.cy;
         s.ct = d.ct;
@@ -163,6 +169,8 @@ struct lbm_batch {
     double* ke_part = nullptr;
     double* ke_ring = nullptr;  // [n][graph_chunk][2]
     double* msum = nullptr;     // 2 x (4 * cells): carried moment sums, ping-pong
+    double* gbuf = nullptr;     // outflow ghost arrays of the instances that have them
+    int64_t gcap = 0;
     int ring_cap = 0;
     hipStream_t cap = nullptr;  // private stream used only for capture
     struct Graph {
@@ -234,7 +242,17 @@ hipError_t launch_batch_step(lbm_batch* b, const double* src, double* dst, bool 
                              hipStream_t st)
 {
     const BatchVariant& V = kBatchVariants[b->variant];
+    // outflow ghosts of the state this step starts from
+    for (int i = 0; i < b->n; ++i) {
+        const BatchInst& d = b->hinst[i];
+        if (d.goff[0] < 0 && d.goff[1] < 0 && d.goff[2] < 0 && d.goff[3] < 0) continue;
+        double* g[4];
+        for (int q = 0; q < 4; ++q) g[q] = d.goff[q] >= 0 ? b->gbuf + d.goff[q] : nullptr;
+        hipError_t e = launch_outflow(src + d.off, d.nx, d.ny, g, b->k, st);
+        if (e != hipSuccess) return e;
+    }
     BatchArgs a;
+    a.gbuf = b->gbuf;
     a.m_in = nullptr;
     a.m_out = nullptr;
     if (V.M == PH_CARRY) {
@@ -246,7 +264,7 @@ hipError_t launch_batch_step(lbm_batch* b, const double* src, double* dst, bool 
             const BatchInst& d = b->hinst[i];
             int np = 0;
             hipError_t e = launch_state(src + d.off, dst + d.off, b->msum + d.moff,
-                                        (int64_t)d.nx * d.ny, d.ct,
+                                        (int64_t)d.nx * d.ny, d.ct, d.ke_axis,
                                         ke ? b->ke_part + 2 * (int64_t)d.kp_off : nullptr, &np,
                                         b->k, st);
             if (e != hipSuccess) return e;
@@ -407,6 +425,11 @@ int lbm_batch_create(const lbm_params* inst, int32_t n, const int64_t* f_offset,
         delete b;
         return bfail(LBM_EINVAL, "batch too large");
     }
+    int64_t gtotal = 0;
+    for (int i = 0; i < n; ++i)
+        for (int q = 0; q < 4; ++q)
+            if (inst[i].bc[q] == LBM_BC_OUTFLOW) gtotal += NV * (int64_t)(q < 2 ? inst[i].ny : inst[i].nx);
+    b->gcap = gtotal;
     b->work_cap = (int)wmax;
     b->ke_cap = (int)std::max<int64_t>(tmax, 2 * NV);
     b->hinst.resize(n);
@@ -415,16 +438,20 @@ int lbm_batch_create(const lbm_params* inst, int32_t n, const int64_t* f_offset,
         (e = hipMalloc(&b->inst, sizeof(BatchInst) * (size_t)n)) != hipSuccess ||
         (e = hipMalloc(&b->work, sizeof(int2) * (size_t)b->work_cap)) != hipSuccess ||
         (e = hipMalloc(&b->msum, sizeof(double) * 8 * (size_t)b->cells)) != hipSuccess ||
+        (e = hipMalloc(&b->gbuf, sizeof(double) * (size_t)(b->gcap > 0 ? b->gcap : 1))) !=
+            hipSuccess ||
         (e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess) {
         lbm_batch_destroy(b);
         return bfail(LBM_ENOMEM, std::string("batch allocation: ") + hipGetErrorString(e));
     }
+    int64_t goff = 0;
     for (int i = 0; i < n; ++i) {
         const lbm_params& q = inst[i];
         BatchInst& d = b->hinst[i];
         std::memset(&d, 0, sizeof(d));
         d.off = b->off[i];
         d.moff = 4 * b->cell_off[i];
+        d.ke_axis = q.ke_axis;
         d.nx = q.nx;
         d.ny = q.ny;
         for (int s = 0; s < 4; ++s) d.bc[s] = q.bc[s];
@@ -432,6 +459,13 @@ int lbm_batch_create(const lbm_params* inst, int32_t n, const int64_t* f_offset,
         d.cy = q.dt / q.dy;
         d.ct = q.dt / q.tau;
         d.dxdy = q.dx * q.dy;
+        for (int sd = 0; sd < 4; ++sd) {
+            d.goff[sd] = -1;
+            if (q.bc[sd] == LBM_BC_OUTFLOW) {
+                d.goff[sd] = goff;
+                goff += NV * (int64_t)(sd < 2 ? q.ny : q.nx);
+            }
+        }
         // fixed-side equilibria by the device equilibrium code
         if ((e = launch_side_eq(b->ke_part, q.side_state, b->k, nullptr)) != hipSuccess ||
             (e = hipDeviceSynchronize()) != hipSuccess ||
@@ -463,6 +497,7 @@ void lbm_batch_destroy(lbm_batch* b)
     if (b->inst) hipFree(b->inst);
     if (b->work) hipFree(b->work);
     if (b->msum) hipFree(b->msum);
+    if (b->gbuf) hipFree(b->gbuf);
     delete b;
 }
 

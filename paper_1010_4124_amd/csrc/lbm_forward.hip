@@ -47,11 +47,11 @@ void k_step(StepArgs a)
 // Eq. (10) summed over the 19 planes in the order phase 1 uses, the cell
 // state (dt/tau rho, T, u/T, v/T) for the step kernel, the rest particle's
 // update (no convection: f_0' = f_0 - dt/tau (f_0 - rho F_0 (1 - u^2/2T)))
-// and per-block (sum, max) partials of rho u_y^2 / 2.
+// and per-block (sum, max) partials of rho u_n^2 / 2.
 __global__ __launch_bounds__(256) void k_state(const double* __restrict__ f,
                                                double* __restrict__ fout,
                                                double* __restrict__ st, int64_t n, double ct,
-                                               double* __restrict__ part, Consts k)
+                                               int ke_axis, double* __restrict__ part, Consts k)
 {
     __shared__ double sr[8];
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -76,8 +76,8 @@ __global__ __launch_bounds__(256) void k_state(const double* __restrict__ f,
         st[n + c] = q.T;
         st[2 * n + c] = q.uxt;
         st[3 * n + c] = q.uyt;
-        const double uy = jy / r;
-        e = 0.5 * r * uy * uy;
+        const double un = (ke_axis ? jx : jy) / r;
+        e = 0.5 * r * un * un;
     }
     if (!part) return;
     const double s = wave_sum(e), mx = wave_max(e);
@@ -162,6 +162,41 @@ __global__ void k_side_eq(double* out, double4 s0, double4 s1, double4 s2, doubl
     out[s * NV + i] = A * feq_poly(eta, t0);
 }
 
+// Outflow ghosts (Sec. IV.A, Eqs. (63)-(64)): for every position p along
+// an outflow side, f^eq of the moments of the nearest interior cell, into
+// g[side][i][p] (length ny for x sides, nx for y sides). blockIdx.y = side.
+__global__ __launch_bounds__(256) void k_outflow(const double* __restrict__ f, int nx, int ny,
+                                                 double* g0, double* g1, double* g2, double* g3,
+                                                 Consts k)
+{
+    const int side = blockIdx.y;
+    double* g = side == 0 ? g0 : side == 1 ? g1 : side == 2 ? g2 : g3;
+    const int len = side < 2 ? ny : nx;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (!g || p >= len) return;
+    const int x = side == 0 ? 0 : side == 1 ? nx - 1 : p;
+    const int y = side < 2 ? p : (side == 2 ? 0 : ny - 1);
+    const int64_t n = (int64_t)nx * ny, c = (int64_t)y * nx + x;
+    double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const double fi = f[i * n + c];
+        r += fi;
+        jx = __builtin_fma(fi, k.vx[i], jx);
+        jy = __builtin_fma(fi, k.vy[i], jy);
+        E = __builtin_fma(fi, k.hv2[i], E);
+    }
+    const CellEq q = cell_eq_from_sums(r, jx, jy, E);
+    const double F1 = weight_c(k, 0, q.T), F2 = weight_c(k, 1, q.T), F3 = weight_c(k, 2, q.T);
+    g[p] = q.rho * (1.0 - 6.0 * (F1 + F2 + F3)) * q.t0;
+#pragma unroll
+    for (int i = 1; i < NV; ++i) {
+        const double A = q.rho * (i < 7 ? F1 : i < 13 ? F2 : F3);
+        const double eta = __builtin_fma(k.vx[i], q.uxt, k.vy[i] * q.uyt);
+        g[(int64_t)i * len + p] = A * feq_poly(eta, q.t0);
+    }
+}
+
 // Moments of Eq. (10) per cell.
 __global__ void k_moments(const double* __restrict__ f, double* __restrict__ rho,
                           double* __restrict__ ux, double* __restrict__ uy,
@@ -185,23 +220,25 @@ __global__ void k_moments(const double* __restrict__ f, double* __restrict__ rho
     T[c] = E / r - 0.5 * (u * u + v * v);
 }
 
-// Transverse kinetic energy partials: one (sum, max) pair per block of 256 cells.
+// Kinetic energy partials of rho u_n^2 / 2 (u_n = u_y, or u_x with ke_axis):
+// one (sum, max) pair per block of 256 cells.
 __global__ __launch_bounds__(256) void k_kinetic_part(const double* __restrict__ f, int64_t n,
-                                                      double* __restrict__ part, Consts k)
+                                                      int ke_axis, double* __restrict__ part,
+                                                      Consts k)
 {
     __shared__ double sr[8];
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double e = 0.0;
     if (c < n) {
-        double r = 0.0, jy = 0.0;
+        double r = 0.0, jn = 0.0;
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
             const double fi = f[i * n + c];
             r += fi;
-            jy = __builtin_fma(fi, k.vy[i], jy);
+            jn = __builtin_fma(fi, ke_axis ? k.vx[i] : k.vy[i], jn);
         }
-        const double uy = jy / r;
-        e = 0.5 * r * uy * uy;
+        const double un = jn / r;
+        e = 0.5 * r * un * un;
     }
     const double s = wave_sum(e), mx = wave_max(e);
     const int w = threadIdx.x >> 6;
@@ -274,7 +311,8 @@ int step_ntiles(int variant, int nx, int ny)
 
 hipError_t launch_step(int variant, const double* fin, double* fout, const Consts& k,
                        double* ke_part, int nx, int ny, const int bc[4], double cx, double cy,
-                       double ct, const double* m_in, double* m_out, hipStream_t st)
+                       double ct, int ke_axis, const double* const gb[4], const double* m_in,
+                       double* m_out, hipStream_t st)
 {
     const StepVariant& V = kStepVariants[variant];
     StepArgs a;
@@ -282,7 +320,11 @@ hipError_t launch_step(int variant, const double* fin, double* fout, const Const
     a.s.fout = fout;
     a.s.nx = nx;
     a.s.ny = ny;
-    for (int j = 0; j < 4; ++j) a.s.bc[j] = bc[j];
+    a.s.ke_axis = ke_axis;
+    for (int j = 0; j < 4; ++j) {
+        a.s.bc[j] = bc[j];
+        a.s.gb[j] = gb ? gb[j] : nullptr;
+    }
     a.s.tiles_x = (nx + TX - 1) / TX;
     a.s.cx = cx;
     a.s.cy = cy;
@@ -298,13 +340,22 @@ hipError_t launch_step(int variant, const double* fin, double* fout, const Const
     return hipGetLastError();
 }
 
+hipError_t launch_outflow(const double* f, int nx, int ny, double* const g[4], const Consts& k,
+                          hipStream_t st)
+{
+    const int len = nx > ny ? nx : ny;
+    hipLaunchKernelGGL(k_outflow, dim3((len + 255) / 256, 4), dim3(256), 0, st, f, nx, ny, g[0],
+                       g[1], g[2], g[3], k);
+    return hipGetLastError();
+}
+
 hipError_t launch_state(const double* f, double* fout, double* state, int64_t n, double ct,
-                        double* part, int* nparts, const Consts& k, hipStream_t st)
+                        int ke_axis, double* part, int* nparts, const Consts& k, hipStream_t st)
 {
     const int64_t blocks = (n + 255) / 256;
     *nparts = (int)blocks;
     hipLaunchKernelGGL(k_state, dim3((unsigned)blocks), dim3(256), 0, st, f, fout, state, n, ct,
-                       part, k);
+                       ke_axis, part, k);
     return hipGetLastError();
 }
 
@@ -347,12 +398,13 @@ hipError_t launch_moments(const double* f, double* rho, double* ux, double* uy, 
     return hipGetLastError();
 }
 
-hipError_t launch_kinetic_part(const double* f, const Consts& k, int64_t n, double* part,
-                               int* nparts, hipStream_t st)
+hipError_t launch_kinetic_part(const double* f, const Consts& k, int64_t n, int ke_axis,
+                               double* part, int* nparts, hipStream_t st)
 {
     const int64_t blocks = (n + 255) / 256;
     *nparts = (int)blocks;
-    hipLaunchKernelGGL(k_kinetic_part, dim3((unsigned)blocks), dim3(256), 0, st, f, n, part, k);
+    hipLaunchKernelGGL(k_kinetic_part, dim3((unsigned)blocks), dim3(256), 0, st, f, n, ke_axis,
+                       part, k);
     return hipGetLastError();
 }
 

@@ -19,6 +19,8 @@ struct lbm_ctx {
     double* ke_part = nullptr;     // [ke_cap][2] diagnostic partials
     double* colbuf = nullptr;      // nx doubles: column sums of lbm_sep_project
     double* msum = nullptr;        // 2 x [4][ny][nx]: carried moment sums (ping-pong)
+    double* gbuf = nullptr;        // outflow ghosts: [19][ny] per x side, [19][nx] per y side
+    double* gb[4] = {nullptr, nullptr, nullptr, nullptr};  // per side into gbuf, or null
 };
 
 int lbmi_validate(const lbm_params* p);
@@ -34,10 +36,13 @@ int step_variant_desc(int v, int info[6]);
 int step_ntiles(int variant, int nx, int ny);
 hipError_t launch_step(int variant, const double* fin, double* fout, const Consts& k,
                        double* ke_part, int nx, int ny, const int bc[4], double cx, double cy,
-                       double ct, const double* m_in, double* m_out, hipStream_t st);
+                       double ct, int ke_axis, const double* const gb[4], const double* m_in,
+                       double* m_out, hipStream_t st);
+hipError_t launch_outflow(const double* f, int nx, int ny, double* const g[4], const Consts& k,
+                          hipStream_t st);
 hipError_t launch_sums(const double* f, double* m, const Consts& k, int64_t n, hipStream_t st);
 hipError_t launch_state(const double* f, double* fout, double* state, int64_t n, double ct,
-                        double* part, int* nparts, const Consts& k, hipStream_t st);
+                        int ke_axis, double* part, int* nparts, const Consts& k, hipStream_t st);
 hipError_t launch_reduce_pairs(const double* part, int n, double dxdy, double* out2,
                                hipStream_t st);
 hipError_t launch_init(const double* rho, const double* ux, const double* uy, const double* T,
@@ -45,8 +50,8 @@ hipError_t launch_init(const double* rho, const double* ux, const double* uy, co
 hipError_t launch_side_eq(double* out, const double s[4][4], const Consts& k, hipStream_t st);
 hipError_t launch_moments(const double* f, double* rho, double* ux, double* uy, double* T,
                           const Consts& k, int64_t n, hipStream_t st);
-hipError_t launch_kinetic_part(const double* f, const Consts& k, int64_t n, double* part,
-                               int* nparts, hipStream_t st);
+hipError_t launch_kinetic_part(const double* f, const Consts& k, int64_t n, int ke_axis,
+                               double* part, int* nparts, hipStream_t st);
 int adj_variant_count();
 int adj_variant_desc(int v, int info[4]);
 hipError_t launch_adjoint(int variant, const double* f, const double* lam1, double* lam0,

@@ -13,8 +13,11 @@
 // kind of the row-load lane and of the halo lane) and resolves ghost rows with
 // uniform logic: a row outside the domain is a periodic wrap, a mirror row of
 // the y-mirrored velocity (reflecting wall), a constant (fixed equilibrium)
-// or unused. Constants and unused slots are substituted when the staged values
-// are written to LDS, so no load result is consumed before it is needed.
+// or unused, or (outflow) a row of the per-step ghost array. Constants and
+// unused slots are substituted when the staged values are written to LDS, so
+// no load result is consumed before it is needed. Outflow ghosts are loaded
+// from the ghost arrays, which hold f^eq of the nearest interior cell per
+// position along the side.
 //
 // ZG ("zero ghosts") stages an adjoint field instead: outside the domain it is
 // the periodic image on periodic axes and zero elsewhere, since ghost cells
@@ -25,13 +28,15 @@
 
 namespace lbmd {
 
-enum { CK_NORM = 0, CK_MIRX = 1, CK_CXLO = 2, CK_CXHI = 3, CK_NONE = 4 };
-enum { RM_NORM = 0, RM_MIRY = 1, RM_CONST = 2, RM_NONE = 3 };
+enum { CK_NORM = 0, CK_MIRX = 1, CK_CXLO = 2, CK_CXHI = 3, CK_NONE = 4, CK_OUTLO = 5, CK_OUTHI = 6 };
+enum { RM_NORM = 0, RM_MIRY = 1, RM_CONST = 2, RM_NONE = 3, RM_OUT = 4 };
 
-// Boundary description of the grid being staged.
+// Boundary description of the grid being staged. gb[s]: the outflow ghost
+// array of side s ([19][ny] for x sides, [19][nx] for y sides), or null.
 struct GridBC {
     int nx, ny;
     int bc[4];
+    const double* gb[4];
 };
 
 template <int R, int H, int PITCH>
@@ -76,6 +81,8 @@ __device__ __forceinline__ void x_source_g(const GridBC& g, int gx, int& col, in
     if (bc == REFLECT) {
         col = lo ? m : g.nx - 1 - m;
         kind = CK_MIRX;
+    } else if (bc == OUTFLOW) {
+        kind = lo ? CK_OUTLO : CK_OUTHI;
     } else {
         kind = lo ? CK_CXLO : CK_CXHI;
     }
@@ -124,6 +131,8 @@ __device__ __forceinline__ RowDesc row_desc_g(const GridBC& g, int gy)
     if (bc == REFLECT) {
         d.mode = RM_MIRY;
         d.src = lo ? m : g.ny - 1 - m;
+    } else if (bc == OUTFLOW) {
+        d.mode = RM_OUT;
     } else {
         d.mode = RM_CONST;
     }
@@ -150,22 +159,39 @@ __device__ __forceinline__ void stage_load_g(const double* __restrict__ field, c
         pre[S::ROWS] = hb[(unsigned)(t.hrow * g.nx + t.hlx + H)];
     } else {
         const int64_t pi = i * plane, px = k.mirx[i] * plane, py = k.miry[i] * plane;
+        const bool mout = t.mkind == CK_OUTLO || t.mkind == CK_OUTHI;
+        const double* xg = t.mkind == CK_OUTLO ? g.gb[XLO] : g.gb[XHI];
 #pragma unroll
         for (int r = 0; r < S::ROWS; ++r) {
             const RowDesc d = row_desc_g<ZG>(g, y0 - H + r);
-            int64_t off;
-            if (d.mode == RM_NORM)
-                off = (t.mkind == CK_MIRX ? px : pi) + (int64_t)d.src * g.nx + t.mcol;
-            else if (d.mode == RM_MIRY)
+            const double* base = field;
+            int64_t off = 0;
+            if (d.mode == RM_NORM) {
+                if (mout) {
+                    base = xg;
+                    off = (int64_t)i * g.ny + d.src;
+                } else {
+                    off = (t.mkind == CK_MIRX ? px : pi) + (int64_t)d.src * g.nx + t.mcol;
+                }
+            } else if (d.mode == RM_MIRY) {
                 off = py + (int64_t)d.src * g.nx + t.mcol;
-            else
-                off = 0;
-            pre[r] = field[off];
+            } else if (d.mode == RM_OUT && t.mkind == CK_NORM) {
+                // (a select, not g.gb[d.side]: a run-time index would put the
+                // descriptor in scratch memory)
+                base = d.side == YLO ? g.gb[YLO] : g.gb[YHI];
+                off = (int64_t)i * g.nx + t.mcol;
+            }
+            pre[r] = base[off];
         }
-        const int64_t hoff = t.hkind == CK_NONE
-                                 ? 0
-                                 : (t.hkind == CK_MIRX ? px : pi) + (int64_t)(y0 + t.hrow) * g.nx + t.hcol;
-        pre[S::ROWS] = field[hoff];
+        const double* hbase = field;
+        int64_t hoff = 0;
+        if (t.hkind == CK_OUTLO || t.hkind == CK_OUTHI) {
+            hbase = t.hkind == CK_OUTLO ? g.gb[XLO] : g.gb[XHI];
+            hoff = (int64_t)i * g.ny + y0 + t.hrow;
+        } else if (t.hkind != CK_NONE) {
+            hoff = (t.hkind == CK_MIRX ? px : pi) + (int64_t)(y0 + t.hrow) * g.nx + t.hcol;
+        }
+        pre[S::ROWS] = hbase[hoff];
     }
 }
 

@@ -42,20 +42,24 @@ constexpr int XPITCH = 65;  // LDS row pitch of the x flux differences
 template <int R>
 using Stage = StageG<R, HALO, PITCH>;
 
-// One grid as seen by a step: states, shape, boundary rules and the ratios
-// dt/dx, dt/dy, dt/tau.
+// One grid as seen by a step: states, shape, boundary rules (with the outflow
+// ghost arrays), the ratios dt/dx, dt/dy, dt/tau and the velocity component
+// of the energy diagnostic (0: u_y, 1: u_x).
 struct StepGrid {
     const double* __restrict__ fin;
     double* __restrict__ fout;
     int nx, ny;
     int bc[4];
     int tiles_x;
+    int ke_axis;
     double cx, cy, ct;
+    const double* gb[4];
 };
 
 __device__ __forceinline__ GridBC grid_bc(const StepGrid& s)
 {
-    return GridBC{s.nx, s.ny, {s.bc[0], s.bc[1], s.bc[2], s.bc[3]}};
+    return GridBC{s.nx, s.ny, {s.bc[0], s.bc[1], s.bc[2], s.bc[3]},
+                  {s.gb[0], s.gb[1], s.gb[2], s.gb[3]}};
 }
 
 // x pass: lane -> (row r = lane % R, strip s = lane / R); the flux
@@ -304,7 +308,7 @@ __device__ __forceinline__ void exchange_sums(double* lds, int wave, int lane, S
 
 // One work item of a step: tile `tile` and, unless the moments are carried,
 // velocity group `grp` (with carried moments the group is the wave's index).
-// ke_dst, if not null, receives the tile's (sum, max) of rho u_y^2 / 2.
+// ke_dst, if not null, receives the tile's (sum, max) of rho u_n^2 / 2.
 // m_in / m_out: PH_CARRY reads and writes the moment sums (rho, j_x, j_y, E,
 // each [ny][nx]); PH_STATE reads the cell state (dt/tau rho, T, u/T, v/T)
 // and leaves the rest particle and the diagnostics to the state pass. lds
@@ -395,8 +399,8 @@ __device__ __forceinline__ void step_work(const StepGrid& a, const Consts& k, SE
             uyt[m] = c.uyt;
             if (!LEAN) t0[m] = c.t0;
             if (act && grp == 0) {
-                const double uy = jy / r;
-                const double e = 0.5 * r * uy * uy;
+                const double un = (a.ke_axis ? jx : jy) / r;
+                const double e = 0.5 * r * un * un;
                 ke_s += e;
                 ke_m = fmax(ke_m, e);
                 // rest particle: no convection, f^eq_0 = rho F_0 (1 - u^2/2T)

@@ -39,6 +39,7 @@ class Setup:
     T: np.ndarray
     side_state: tuple = (None, None, None, None)
     meta: dict = field(default_factory=dict)
+    ke_axis: int = 0  # velocity component of the energy diagnostic: 0 u_y, 1 u_x
 
     def fields(self):
         return self.rho, self.ux, self.uy, self.T
@@ -130,6 +131,31 @@ def khi(nx=512, ny=512, dx=1e-3, dy=1e-3, dt=1e-5, tau=1e-5, Dv=0.02, Drho=0.02,
                  rho, ux, np.ascontiguousarray(uy), T, (None,) * 4,
                  {"workload": "khi", "Dv": Dv, "Drho": Drho, "rho1": rho1, "rho2": rho2,
                   "u0": u0, "p0": p0, "yw": yw})
+
+
+def khi_paper(nx=600, ny=200, dx=1e-3, dy=1e-3, dt=1e-5, tau=1e-5, Dv=4e-3, Drho=8e-3,
+              rhoL=5.0, rhoR=2.0, vL=0.5, vR=-0.5, p0=2.5, u0=0.02, k=10 * np.pi):
+    """The paper's own shear layer (Sec. IV.A, Eqs. (59)-(62)): interface
+    normal to x at x = 0 (x_i = (i + 1/2) dx - L_x / 2), flow along y,
+    periodic in y, outflow sides in x (Eqs. (63)-(64)).
+
+    rho(x) = (rhoL + rhoR)/2 - (rhoL - rhoR)/2 tanh(x / Drho),
+    v(x)   = (vL + vR)/2 - (vL - vR)/2 tanh(x / Dv),     uniform p0 (T = p0 / rho),
+    u      = u0 sin(k y) exp(-k |x|)    (Eq. (62) read with |x|: the printed
+                                         exp(-k x) grows without bound for x < 0).
+    The growth diagnostic is rho u_x^2 / 2 (ke_axis = 1). The paper's widths
+    4, 8, ... are grid spacings: Dv = 4 dx by default."""
+    x = (np.arange(nx) + 0.5) * dx - 0.5 * nx * dx
+    y = (np.arange(ny) + 0.5) * dy
+    rho1d = 0.5 * (rhoL + rhoR) - 0.5 * (rhoL - rhoR) * np.tanh(x / Drho)
+    v1d = 0.5 * (vL + vR) - 0.5 * (vL - vR) * np.tanh(x / Dv)
+    rho = np.tile(rho1d, (ny, 1))
+    uy = np.tile(v1d, (ny, 1))
+    ux = u0 * np.sin(k * y)[:, None] * np.exp(-k * np.abs(x))[None, :]
+    T = p0 / rho
+    return Setup(nx, ny, dx, dy, dt, tau, (OUTFLOW, OUTFLOW, PERIODIC, PERIODIC), rho, ux, uy, T,
+                 meta=dict(Dv=Dv, Drho=Drho, rhoL=rhoL, rhoR=rhoR, vL=vL, vR=vR, p0=p0, u0=u0,
+                           k=k), ke_axis=1)
 
 
 def khi_tangents(nx, ny, dx, dy, Dv, Drho, rho1=5.0, rho2=2.0, u0=0.5, p0=2.5, yw=0.02):

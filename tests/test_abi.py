@@ -56,9 +56,13 @@ def test_create_rejects_bad_params_without_gpu():
         h = C.c_void_p()
         assert L.lbm_create(C.byref(p), C.byref(h)) == lbm.LBM_EINVAL
         assert L.lbm_last_error()
-    p = lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5, bc=(3, 3, 0, 0))
-    h = C.c_void_p()
-    assert L.lbm_create(C.byref(p), C.byref(h)) == lbm.LBM_EUNSUPPORTED
+    for p in (lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5, ke_axis=2),
+              lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5, bc=(3, 3, 0, 0), ke_axis=-1)):
+        h = C.c_void_p()
+        assert L.lbm_create(C.byref(p), C.byref(h)) == lbm.LBM_EINVAL
+    p = lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5)
+    p.reserved = 1
+    assert L.lbm_create(C.byref(p), C.byref(h)) == lbm.LBM_EINVAL
 
 
 def test_batch_create_rejects_bad_instances_without_gpu():
@@ -77,13 +81,13 @@ def test_batch_create_rejects_bad_instances_without_gpu():
     other_vk = lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5, vk=(1.0, 2.0, 3.5))
     other_eps = lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5, eps=1e-7)
     bad = lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 0.0)
-    outflow = lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5, bc=(3, 3, 0, 0))
+    bad_axis = lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5, ke_axis=3)
     h = C.c_void_p()
     assert L.lbm_batch_create(None, 1, None, C.byref(h)) == lbm.LBM_EINVAL
     assert create([good, other_vk]) == lbm.LBM_EINVAL
     assert create([good, other_eps]) == lbm.LBM_EINVAL
     assert create([good, bad]) == lbm.LBM_EINVAL
-    assert create([good, outflow]) == lbm.LBM_EUNSUPPORTED
+    assert create([good, bad_axis]) == lbm.LBM_EINVAL
     n = 19 * 64
     assert create([good, good], [0, n - 1]) == lbm.LBM_EINVAL     # overlapping blocks
     assert create([good, good], [n, 0 + 5]) == lbm.LBM_EINVAL     # overlapping, reversed

@@ -89,3 +89,16 @@ def test_sep_project():
     got = ctx.sep_project(torch.from_numpy(g).cuda(), A, B).cpu().numpy()
     ref = A @ (B @ g)
     assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_reverse_step_rejects_outflow_and_x_energy():
+    """The reverse step differentiates E_y with walls, periodic or fixed
+    sides; outflow sides and the u_x diagnostic are refused, not guessed."""
+    f = None
+    for bc, axis in (((3, 3, P, P), 0), ((P, P, R, R), 1)):
+        ctx = lbm.Context(24, 16, 1e-2, 1e-2, 1e-4, 1e-4, bc, ke_axis=axis)
+        s = inputs.random_fields(24, 16, 9)
+        f = ctx.init(*s)
+        with pytest.raises(lbm.LbmError) as ei:
+            ctx.adjoint_step(f, torch.zeros_like(f), 1.0)
+        assert ei.value.code == lbm.LBM_EUNSUPPORTED
