@@ -17,7 +17,8 @@ the stream the kernel runs on bracket the timed region, which holds exactly
 measured HBM traffic per launch from the committed rocprofv3 counter summary
 when it was taken on the current kernel sources. `extra` holds the other
 workloads: the 2048^2 forward step, the adjoint (reverse step alone and the
-full checkpointed gradient) and the 64-instance batched sweep. `cpu_baseline`
+full checkpointed gradient), the 64-instance batched sweep and the paper's
+transition-layer studies on its own shear layer. `cpu_baseline`
 is the CPU oracle timed on a bounded sample of the main workload.
 
 Other modes (for the rocprofv3 runs whose summaries live in profiles/):
@@ -256,6 +257,19 @@ def bench_batch(args):
     return r
 
 
+def bench_paper_studies():
+    """The paper's own shear layer (outflow sides) as batched studies of the
+    velocity- and density-layer widths: growth rates, fits, throughput."""
+    from paper_1010_4124_amd import sweeps
+    v = sweeps.velocity_study()
+    d = sweeps.density_study()
+    r = {"velocity_layer": {k: v[k] for k in ("widths", "gamma", "a", "b", "mlups", "steps")},
+         "density_layer": {k: d[k] for k in ("widths", "gamma", "c", "e", "mlups", "steps")},
+         "note": "widths in grid spacings; gamma from ln E_x|max over t in [0.1, 0.3]"}
+    log(f"paper studies: {r}")
+    return r
+
+
 def cpu_baseline(setup, seconds):
     import oracle
     p = oracle.OracleParams.make(setup.nx, setup.ny, setup.dx, setup.dy, setup.dt, setup.tau,
@@ -422,6 +436,7 @@ def main():
     if not args.no_extra:
         extra["forward_2048"] = bench_forward_large(args)
         extra["batched_sweep"] = bench_batch(args)
+        extra["paper_studies"] = bench_paper_studies()
         extra["adjoint"] = bench_adjoint(args)
 
     out = {
