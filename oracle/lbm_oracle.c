@@ -51,6 +51,8 @@ typedef struct {
     double vk[3];             /* particle speeds v_1, v_2, v_3 */
     double eps;               /* WENO regulariser, 1e-6 in Eq. (52) */
     double side_state[4][4];  /* (rho, ux, uy, T) of each FIXED_EQ side */
+    int32_t scheme;           /* convection: 0 WENO5, 1 first-, 2 second-order upwind */
+    int32_t pad;
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -314,6 +316,36 @@ void orc_weno5_grad(double a, double b, double c, double d, double e, double eps
     weno5_bar(a, b, c, d, e, eps, 1.0, g);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Comparison schemes of Sec. III.B (Fig. 2): the numerical flux at face      */
+/* I+1/2 from the upwind-ordered samples (a, b, c, d, e) = F_{I-2..I+2} (the  */
+/* same ordering as the WENO5 face; c is the upwind cell I).                  */
+/*   first-order upwind:  h = c                                               */
+/*   second-order upwind: h = c + (c - b) / 2   (linear extrapolation from    */
+/*                        the two upwind cells)                               */
+/* ------------------------------------------------------------------------ */
+static double face_value(int scheme, double a, double b, double c, double d, double e, double eps)
+{
+    if (scheme == 1) return c;
+    if (scheme == 2) return c + 0.5 * (c - b);
+    return orc_weno5(a, b, c, d, e, eps);
+}
+
+/* Face fluxes of a periodic line of n values F[0..n-1] with any scheme:
+ * h[I] is the flux at face I+1/2, upwinded to the left for sign >= 0 and to
+ * the right (mirror image) for sign < 0. */
+void orc_scheme_periodic_line(const double* F, int n, int sign, int scheme, double eps, double* h)
+{
+#define W(j) F[(((j) % n) + n) % n]
+    for (int I = 0; I < n; ++I) {
+        if (sign >= 0)
+            h[I] = face_value(scheme, W(I - 2), W(I - 1), W(I), W(I + 1), W(I + 2), eps);
+        else
+            h[I] = face_value(scheme, W(I + 3), W(I + 2), W(I + 1), W(I), W(I - 1), eps);
+    }
+#undef W
+}
+
 /* Face fluxes of a periodic line of n values F[0..n-1]: h[I] is the flux at
  * face I+1/2, upwinded to the left for sign >= 0 and to the right (mirror
  * image) for sign < 0. */
@@ -359,6 +391,7 @@ static int check_params(const orc_params* p)
     if ((p->bc[XLO] == BC_PERIODIC) != (p->bc[XHI] == BC_PERIODIC)) return -1;
     if ((p->bc[YLO] == BC_PERIODIC) != (p->bc[YHI] == BC_PERIODIC)) return -1;
     if (p->vk[0] == p->vk[1] || p->vk[1] == p->vk[2] || p->vk[0] == p->vk[2]) return -1;
+    if (p->scheme < 0 || p->scheme > 2) return -1;
     return 0;
 }
 
@@ -489,22 +522,24 @@ int orc_moments(const orc_params* p, const double* f, double* rho, double* ux, d
 /* with the fluxes of Eq. (48) upwinded by the sign of v_a.                  */
 /* ------------------------------------------------------------------------ */
 static double face_flux_x(const grid* g, const double* fp, int i, double v, int y, int x,
-                          double eps)
+                          double eps, int scheme)
 {
     /* face x+1/2 of row y, F = v f */
 #define FX(xx) (v * fp[P(g, i, y, (xx))])
-    if (v >= 0.0) return orc_weno5(FX(x - 2), FX(x - 1), FX(x), FX(x + 1), FX(x + 2), eps);
-    return orc_weno5(FX(x + 3), FX(x + 2), FX(x + 1), FX(x), FX(x - 1), eps);
+    if (v >= 0.0)
+        return face_value(scheme, FX(x - 2), FX(x - 1), FX(x), FX(x + 1), FX(x + 2), eps);
+    return face_value(scheme, FX(x + 3), FX(x + 2), FX(x + 1), FX(x), FX(x - 1), eps);
 #undef FX
 }
 
 static double face_flux_y(const grid* g, const double* fp, int i, double v, int y, int x,
-                          double eps)
+                          double eps, int scheme)
 {
     /* face y+1/2 of column x */
 #define FY(yy) (v * fp[P(g, i, (yy), x)])
-    if (v >= 0.0) return orc_weno5(FY(y - 2), FY(y - 1), FY(y), FY(y + 1), FY(y + 2), eps);
-    return orc_weno5(FY(y + 3), FY(y + 2), FY(y + 1), FY(y), FY(y - 1), eps);
+    if (v >= 0.0)
+        return face_value(scheme, FY(y - 2), FY(y - 1), FY(y), FY(y + 1), FY(y + 2), eps);
+    return face_value(scheme, FY(y + 3), FY(y + 2), FY(y + 1), FY(y), FY(y - 1), eps);
 #undef FY
 }
 
@@ -533,11 +568,11 @@ static int step_once(const orc_params* p, const vset* V, double geq[4][NV], cons
             for (int i = 0; i < NV; ++i) {
                 double dhx = 0.0, dhy = 0.0;
                 if (V->vx[i] != 0.0)
-                    dhx = face_flux_x(&g, fp, i, V->vx[i], y, x, p->eps) -
-                          face_flux_x(&g, fp, i, V->vx[i], y, x - 1, p->eps);
+                    dhx = face_flux_x(&g, fp, i, V->vx[i], y, x, p->eps, p->scheme) -
+                          face_flux_x(&g, fp, i, V->vx[i], y, x - 1, p->eps, p->scheme);
                 if (V->vy[i] != 0.0)
-                    dhy = face_flux_y(&g, fp, i, V->vy[i], y, x, p->eps) -
-                          face_flux_y(&g, fp, i, V->vy[i], y - 1, x, p->eps);
+                    dhy = face_flux_y(&g, fp, i, V->vy[i], y, x, p->eps, p->scheme) -
+                          face_flux_y(&g, fp, i, V->vy[i], y - 1, x, p->eps, p->scheme);
                 double fi = f[C(&g, i, y, x)];
                 fo[C(&g, i, y, x)] = fi - cx * dhx - cy * dhy - ct * (fi - fe[i]);
             }
@@ -608,6 +643,7 @@ int orc_adjoint_step(const orc_params* p, const double* f_n, const double* lam1,
                      double* lam_n)
 {
     if (check_params(p)) return -1;
+    if (p->scheme != 0) return -2; /* the reverse mode covers WENO5 only */
     for (int s = 0; s < 4; ++s)
         if (p->bc[s] == BC_OUTFLOW) return -2;
     vset V;

@@ -26,7 +26,8 @@ NV = 19
 
 __all__ = [
     "OracleParams", "build_oracle", "lib", "velocity_table", "weights", "feq_cell",
-    "moments_cell", "weno5", "weno5_grad", "weno_periodic_line", "init", "moments",
+    "moments_cell", "weno5", "weno5_grad", "weno_periodic_line", "scheme_periodic_line",
+    "init", "moments",
     "step", "kinetic_y", "kinetic_y_grad", "adjoint_step", "init_vjp", "feq_partials",
     "PERIODIC", "FIXED_EQ", "REFLECT", "OUTFLOW", "NV",
 ]
@@ -50,12 +51,14 @@ class OracleParams(C.Structure):
         ("dx", C.c_double), ("dy", C.c_double), ("dt", C.c_double), ("tau", C.c_double),
         ("vk", C.c_double * 3), ("eps", C.c_double),
         ("side_state", (C.c_double * 4) * 4),
+        ("scheme", C.c_int32), ("pad", C.c_int32),
     ]
 
     @classmethod
     def make(cls, nx, ny, dx, dy, dt, tau, bc=(PERIODIC,) * 4, vk=(1.0, 2.0, 3.0),
-             eps=1e-6, side_state=None):
+             eps=1e-6, side_state=None, scheme=0):
         p = cls()
+        p.scheme = int(scheme)  # 0 WENO5, 1 first-order, 2 second-order upwind
         p.nx, p.ny = int(nx), int(ny)
         for s in range(4):
             p.bc[s] = int(bc[s])
@@ -95,6 +98,8 @@ def lib():
         _lib.orc_weno5_grad.restype = None
         _lib.orc_weno_periodic_line.argtypes = [pd, C.c_int, C.c_int, d, pd]
         _lib.orc_weno_periodic_line.restype = None
+        _lib.orc_scheme_periodic_line.argtypes = [pd, C.c_int, C.c_int, C.c_int, d, pd]
+        _lib.orc_scheme_periodic_line.restype = None
         _lib.orc_init.argtypes = [pp, pd, pd, pd, pd, pd]
         _lib.orc_moments.argtypes = [pp, pd, pd, pd, pd, pd]
         _lib.orc_step.argtypes = [pp, pd, pd, C.c_int, C.c_int]
@@ -178,6 +183,15 @@ def weno_periodic_line(F, sign=1, eps=1e-6):
     F = _f64(F)
     h = np.zeros_like(F)
     lib().orc_weno_periodic_line(_p(F), F.size, int(sign), float(eps), _p(h))
+    return h
+
+
+def scheme_periodic_line(F, sign=1, scheme=0, eps=1e-6):
+    """Face fluxes h[I] at I+1/2 of a periodic line with scheme 0 (WENO5),
+    1 (first-order upwind) or 2 (second-order upwind)."""
+    F = _f64(F)
+    h = np.zeros_like(F)
+    lib().orc_scheme_periodic_line(_p(F), F.size, int(sign), int(scheme), float(eps), _p(h))
     return h
 
 
