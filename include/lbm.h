@@ -74,16 +74,30 @@ typedef struct {
     int32_t ke_axis;           /* velocity component u_n of the kinetic-energy
                                   diagnostics rho u_n^2 / 2: 0 = u_y, 1 = u_x
                                   (the interface normal; Sec. IV uses u_x) */
-    int32_t reserved;          /* must be 0 */
+    int32_t scheme;            /* convection flux of lbm_step (Sec. III.B, Fig. 2):
+                                  LBM_SCHEME_WENO5 (the method), or one of the
+                                  two upwind schemes the paper compares it with;
+                                  anything else is LBM_EINVAL. Only WENO5 has a
+                                  reverse step, step variants and a batch path
+                                  (LBM_EUNSUPPORTED otherwise) */
 } lbm_params;
+
+enum {
+    LBM_SCHEME_WENO5 = 0,    /* fifth-order WENO faces, Eqs. (48)-(55) */
+    LBM_SCHEME_UPWIND1 = 1,  /* first-order upwind: the face takes the upwind
+                                cell's flux v f */
+    LBM_SCHEME_UPWIND2 = 2   /* second-order upwind: the upwind cell's flux
+                                plus half its difference to the next cell
+                                upstream, F_I + (F_I - F_{I-1}) / 2 for v > 0
+                                and the mirror image for v < 0 */
+};
 
 typedef struct lbm_ctx lbm_ctx;
 
 /* Validate `p` and create a context. Allocates on the current device: one
  * 19-plane ping-pong state (used by lbm_step when nsteps > 1), per-tile
  * diagnostic partials and the fixed-side equilibria. Synchronous.
- * Errors: LBM_EINVAL (null or invalid parameters), LBM_EUNSUPPORTED
- * (an outflow side), LBM_ENOMEM, LBM_EHIP. */
+ * Errors: LBM_EINVAL (null or invalid parameters), LBM_ENOMEM, LBM_EHIP. */
 int lbm_create(const lbm_params* p, lbm_ctx** out);
 
 /* Free a context and its device buffers (synchronises the device). NULL is
@@ -97,8 +111,9 @@ int lbm_init(lbm_ctx* ctx, const double* rho, const double* ux, const double* uy
 
 /* Advance nsteps >= 1 forward-Euler steps (Eq. (47)) from f_in; the result
  * lands in f_out and f_in is left unchanged. Each step computes, per cell,
- * the moments of Eq. (10) from f, f^eq, the WENO5 flux differences of every
- * velocity along x and y and the BGK relaxation.
+ * the moments of Eq. (10) from f, f^eq, the flux differences of every
+ * velocity along x and y (WENO5, or the upwind scheme that p.scheme names:
+ * one thread per cell, a plain comparison kernel) and the BGK relaxation.
  * ke_log: NULL, or device double[2*nsteps] receiving for each step n the
  * transverse kinetic energy of the state the step starts from,
  * ke_log[2n] = sum_cells rho u_n^2 / 2 * dx * dy and ke_log[2n+1] =
@@ -120,8 +135,8 @@ int lbm_kinetic_y(lbm_ctx* ctx, const double* f, double* out2, lbm_stream stream
 /* Discrete adjoint of one step (reverse mode of lbm_step with nsteps = 1):
  *   lam_n = (dS/df)^T lam_np1 + w dE_y/df,   S = the step of Eq. (47),
  * evaluated at f = f_n, with E_y = sum_cells rho u_y^2 / 2 * dx * dy (the
- * objective is E_y: ke_axis must be 0, and outflow sides are not supported:
- * LBM_EUNSUPPORTED). The
+ * objective is E_y: ke_axis must be 0; outflow sides and schemes other than
+ * WENO5 are not supported: LBM_EUNSUPPORTED). The
  * transpose covers the WENO5 fluxes including their nonlinear weights
  * (Eqs. (48)-(55)), the equilibrium through the moments (Eqs. (10), (28),
  * (44)-(46)), the BGK term and the ghost layers (periodic images, mirrored
@@ -195,7 +210,9 @@ int lbm_get_step_variant(lbm_ctx* ctx, int32_t* variant);
  * lbm_step from f_in into f_tmp (f_in is not modified), bracketed by HIP
  * events on `stream`. ms_out: NULL or host double[nv or count] receiving
  * milliseconds per step. Leaves the fastest variant selected. Synchronous
- * (waits for the timed work); on error the previous variant is kept. */
+ * (waits for the timed work); on error the previous variant is kept.
+ * LBM_EUNSUPPORTED when the context's scheme is not WENO5 (the variants are
+ * WENO5 kernels). */
 int lbm_tune_step(lbm_ctx* ctx, const double* f_in, double* f_tmp, int32_t nsteps,
                   const int32_t* variants, int32_t nv, double* ms_out, lbm_stream stream);
 
@@ -222,7 +239,8 @@ typedef struct lbm_batch lbm_batch;
  * per-tile partials, the device descriptor table and the work list, and a
  * private stream used only to capture graphs. Synchronous.
  * Errors: LBM_EINVAL (invalid instance, differing vk or weno_eps,
- * overlapping or negative offsets), LBM_EUNSUPPORTED, LBM_ENOMEM, LBM_EHIP. */
+ * overlapping or negative offsets), LBM_EUNSUPPORTED (an instance with a
+ * scheme other than WENO5), LBM_ENOMEM, LBM_EHIP. */
 int lbm_batch_create(const lbm_params* inst, int32_t n, const int64_t* f_offset,
                      lbm_batch** out);
 

@@ -59,7 +59,8 @@ int lbmi_validate(const lbm_params* p)
             return fail(LBM_EINVAL, "fixed-equilibrium side needs rho > 0 and T > 0%s%lld");
     }
     if (p->ke_axis != 0 && p->ke_axis != 1) return fail(LBM_EINVAL, "ke_axis must be 0 or 1%s%lld");
-    if (p->reserved != 0) return fail(LBM_EINVAL, "reserved must be 0%s%lld");
+    if (p->scheme < LBM_SCHEME_WENO5 || p->scheme > LBM_SCHEME_UPWIND2)
+        return fail(LBM_EINVAL, "unknown scheme%s%lld");
     if ((p->bc[0] == LBM_BC_PERIODIC) != (p->bc[1] == LBM_BC_PERIODIC) ||
         (p->bc[2] == LBM_BC_PERIODIC) != (p->bc[3] == LBM_BC_PERIODIC))
         return fail(LBM_EINVAL, "periodic must be set on both sides of an axis%s%lld");
@@ -198,6 +199,26 @@ int lbm_step(lbm_ctx* c, const double* f_in, double* f_out, int32_t nsteps, doub
     hipStream_t st = (hipStream_t)stream;
     const lbm_params& p = c->p;
     const double cx = p.dt / p.dx, cy = p.dt / p.dy, ct = p.dt / p.tau;
+    if (p.scheme != LBM_SCHEME_WENO5) {
+        // comparison schemes: one cell-parallel kernel per step
+        for (int s = 0; s < nsteps; ++s) {
+            const double* src = s == 0 ? f_in : (((nsteps - s) % 2 == 0) ? f_out : c->scratch);
+            double* dst = ((nsteps - 1 - s) % 2 == 0) ? f_out : c->scratch;
+            hipError_t e = hipSuccess;
+            if (c->gb[0] || c->gb[1] || c->gb[2] || c->gb[3])
+                e = launch_outflow(src, p.nx, p.ny, c->gb, c->k, st);
+            if (e != hipSuccess) return hip_fail(e, "lbm_step outflow");
+            int nparts = 0;
+            e = launch_step_lo(p.scheme, src, dst, c->k, ke_log ? c->ke_part : nullptr, &nparts,
+                               p.nx, p.ny, p.bc, cx, cy, ct, p.ke_axis, c->gb, st);
+            if (e != hipSuccess) return hip_fail(e, "lbm_step");
+            if (ke_log) {
+                e = launch_reduce_pairs(c->ke_part, nparts, p.dx * p.dy, ke_log + 2 * s, st);
+                if (e != hipSuccess) return hip_fail(e, "lbm_step ke");
+            }
+        }
+        return LBM_OK;
+    }
     const int ntiles = step_ntiles(c->variant, p.nx, p.ny);
     int info[6];
     step_variant_desc(c->variant, info);
@@ -320,6 +341,8 @@ int lbm_adjoint_step(lbm_ctx* c, const double* f_n, const double* lam_np1, doubl
             return fail(LBM_EUNSUPPORTED, "the reverse step has no outflow sides%s%lld");
     if (p.ke_axis != 0)
         return fail(LBM_EUNSUPPORTED, "the reverse step's objective is E_y (ke_axis 0)%s%lld");
+    if (p.scheme != LBM_SCHEME_WENO5)
+        return fail(LBM_EUNSUPPORTED, "the reverse step is the WENO5 scheme's%s%lld");
     const size_t fb = NV * (size_t)p.nx * p.ny * sizeof(double);
     if (overlaps(lam_n, fb, lam_np1, fb) || overlaps(lam_n, fb, f_n, fb))
         return fail(LBM_EINVAL, "lam_n overlaps an input%s%lld");
@@ -368,6 +391,8 @@ int lbm_tune_step(lbm_ctx* c, const double* f_in, double* f_tmp, int32_t nsteps,
 {
     if (!c || !f_in || !f_tmp || nsteps < 1 || nv < 0 || (nv > 0 && !variants))
         return fail(LBM_EINVAL, "bad argument%s%lld");
+    if (c->p.scheme != LBM_SCHEME_WENO5)
+        return fail(LBM_EUNSUPPORTED, "step variants are WENO5 kernels%s%lld");
     const int count = nv > 0 ? nv : step_variant_count();
     for (int j = 0; j < count; ++j) {
         const int v = nv > 0 ? variants[j] : j;

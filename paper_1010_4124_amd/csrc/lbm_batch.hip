@@ -366,6 +366,8 @@ int lbm_batch_create(const lbm_params* inst, int32_t n, const int64_t* f_offset,
     for (int i = 0; i < n; ++i) {
         const int rc = lbmi_validate(&inst[i]);
         if (rc) return rc;
+        if (inst[i].scheme != LBM_SCHEME_WENO5)
+            return bfail(LBM_EUNSUPPORTED, "the batched step is the WENO5 scheme's");
         if (std::memcmp(inst[i].vk, inst[0].vk, sizeof(inst[0].vk)) != 0 ||
             std::memcmp(&inst[i].weno_eps, &inst[0].weno_eps, sizeof(double)) != 0)
             return bfail(LBM_EINVAL, "instances of a batch must share vk and weno_eps");

@@ -38,6 +38,10 @@ hipError_t launch_step(int variant, const double* fin, double* fout, const Const
                        double* ke_part, int nx, int ny, const int bc[4], double cx, double cy,
                        double ct, int ke_axis, const double* const gb[4], const double* m_in,
                        double* m_out, hipStream_t st);
+hipError_t launch_step_lo(int scheme, const double* fin, double* fout, const Consts& k,
+                          double* ke_part, int* nparts, int nx, int ny, const int bc[4],
+                          double cx, double cy, double ct, int ke_axis,
+                          const double* const gb[4], hipStream_t st);
 hipError_t launch_outflow(const double* f, int nx, int ny, double* const g[4], const Consts& k,
                           hipStream_t st);
 hipError_t launch_sums(const double* f, double* m, const Consts& k, int64_t n, hipStream_t st);

@@ -40,6 +40,7 @@ class Setup:
     side_state: tuple = (None, None, None, None)
     meta: dict = field(default_factory=dict)
     ke_axis: int = 0  # velocity component of the energy diagnostic: 0 u_y, 1 u_x
+    scheme: int = 0   # convection flux: 0 WENO5, 1 first-order upwind, 2 second-order upwind
 
     def fields(self):
         return self.rho, self.ux, self.uy, self.T

@@ -22,6 +22,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "lbm.h")
 
 NV = 19
 PERIODIC, FIXED_EQ, REFLECT, OUTFLOW = 0, 1, 2, 3
+WENO5, UPWIND1, UPWIND2 = 0, 1, 2  # lbm_params.scheme
 LBM_OK, LBM_EINVAL, LBM_EUNSUPPORTED, LBM_EHIP, LBM_ENOMEM = 0, -1, -2, -3, -4
 
 
@@ -37,15 +38,15 @@ class LbmParams(C.Structure):
         ("dx", C.c_double), ("dy", C.c_double), ("dt", C.c_double), ("tau", C.c_double),
         ("vk", C.c_double * 3), ("weno_eps", C.c_double),
         ("side_state", (C.c_double * 4) * 4),
-        ("ke_axis", C.c_int32), ("reserved", C.c_int32),
+        ("ke_axis", C.c_int32), ("scheme", C.c_int32),
     ]
 
     @classmethod
     def make(cls, nx, ny, dx, dy, dt, tau, bc=(PERIODIC,) * 4, vk=(1.0, 2.0, 3.0), eps=1e-6,
-             side_state=None, ke_axis=0):
+             side_state=None, ke_axis=0, scheme=WENO5):
         p = cls()
         p.ke_axis = int(ke_axis)
-        p.reserved = 0
+        p.scheme = int(scheme)
         p.nx, p.ny = int(nx), int(ny)
         for s in range(4):
             p.bc[s] = int(bc[s])
@@ -394,7 +395,8 @@ class Batch:
     @classmethod
     def from_setups(cls, setups, f_offset=None):
         return cls([LbmParams.make(s.nx, s.ny, s.dx, s.dy, s.dt, s.tau, s.bc,
-                                   side_state=s.side_state, ke_axis=getattr(s, "ke_axis", 0))
+                                   side_state=s.side_state, ke_axis=getattr(s, "ke_axis", 0),
+                                   scheme=getattr(s, "scheme", WENO5))
                     for s in setups], f_offset)
 
     def close(self):
@@ -470,8 +472,9 @@ class Context:
     """Owns one lbm_ctx* for a grid and its parameters."""
 
     def __init__(self, nx, ny, dx, dy, dt, tau, bc=(PERIODIC,) * 4, vk=(1.0, 2.0, 3.0),
-                 eps=1e-6, side_state=None, ke_axis=0):
-        self.params = LbmParams.make(nx, ny, dx, dy, dt, tau, bc, vk, eps, side_state, ke_axis)
+                 eps=1e-6, side_state=None, ke_axis=0, scheme=WENO5):
+        self.params = LbmParams.make(nx, ny, dx, dy, dt, tau, bc, vk, eps, side_state, ke_axis,
+                                     scheme)
         self.nx, self.ny = int(nx), int(ny)
         self.handle = lbm_create(self.params)
         self.device = torch.device("cuda", torch.cuda.current_device())
@@ -479,7 +482,7 @@ class Context:
     @classmethod
     def from_setup(cls, s, **kw):
         return cls(s.nx, s.ny, s.dx, s.dy, s.dt, s.tau, s.bc, side_state=s.side_state,
-                   ke_axis=getattr(s, "ke_axis", 0), **kw)
+                   ke_axis=getattr(s, "ke_axis", 0), scheme=getattr(s, "scheme", WENO5), **kw)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -60,9 +60,9 @@ def test_create_rejects_bad_params_without_gpu():
               lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5, bc=(3, 3, 0, 0), ke_axis=-1)):
         h = C.c_void_p()
         assert L.lbm_create(C.byref(p), C.byref(h)) == lbm.LBM_EINVAL
-    p = lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5)
-    p.reserved = 1
-    assert L.lbm_create(C.byref(p), C.byref(h)) == lbm.LBM_EINVAL
+    for bad_scheme in (-1, 3):
+        p = lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5, scheme=bad_scheme)
+        assert L.lbm_create(C.byref(p), C.byref(h)) == lbm.LBM_EINVAL
 
 
 def test_batch_create_rejects_bad_instances_without_gpu():
@@ -88,6 +88,10 @@ def test_batch_create_rejects_bad_instances_without_gpu():
     assert create([good, other_eps]) == lbm.LBM_EINVAL
     assert create([good, bad]) == lbm.LBM_EINVAL
     assert create([good, bad_axis]) == lbm.LBM_EINVAL
+    # the batched step is WENO5's only
+    assert create([good, lbm.LbmParams.make(8, 8, 1e-3, 1e-3, 1e-5, 1e-5,
+                                            scheme=lbm.UPWIND1)]) == lbm.LBM_EUNSUPPORTED
+    assert b"WENO5" in L.lbm_last_error()
     n = 19 * 64
     assert create([good, good], [0, n - 1]) == lbm.LBM_EINVAL     # overlapping blocks
     assert create([good, good], [n, 0 + 5]) == lbm.LBM_EINVAL     # overlapping, reversed
