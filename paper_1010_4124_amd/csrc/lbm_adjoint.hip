@@ -349,8 +349,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_
     const int x0 = tx * ATX, y0 = ty * R;
     const int64_t plane = (int64_t)a.nx * a.ny;
     const int gx = x0 + lane;
-    const bool interior =
-        x0 >= FH && x0 + ATX + FH <= a.nx && y0 >= FH && y0 + R + FH <= a.ny;
+    const bool interior = fast_tile(grid_of(a), x0, y0, ATX, R, FH);
 
     // ---- phase 1: per-cell adjoint of the equilibrium and the objective ----
     double K0[R], Kx[R], Ky[R], KE[R];

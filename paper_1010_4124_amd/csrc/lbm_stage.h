@@ -8,7 +8,8 @@
 // from one more load in which lane l < 2HR takes row l/(2H) and one of the
 // halo columns. A plane costs R+2H+1 loads per lane.
 //
-// Interior tiles (tile plus halo inside the domain) need nothing else. A tile
+// Fast tiles (tile plus halo inside the domain, or halo columns wrapping
+// once around a periodic x axis: fast_tile) need nothing else. A tile
 // touching the boundary gets a per-lane column map once (source column and
 // kind of the row-load lane and of the halo lane) and resolves ghost rows with
 // uniform logic: a row outside the domain is a periodic wrap, a mirror row of
@@ -52,7 +53,9 @@ struct StageG {
 struct TileMapG {
     int hrow, hlx;    // halo lane: tile row and column (-H..-1, 64..63+H)
     int mcol, mkind;  // row-load lane: source column and kind (boundary tiles)
-    int hcol, hkind;  // halo lane: source column and kind (boundary tiles)
+    int hcol, hkind;  // halo lane: source column and kind (boundary tiles);
+                      // fast tiles: hcol = offset of the halo value from the
+                      // start of the tile's first row (periodic image)
 };
 
 // Source column of global column gx for a row inside the domain. Ghost
@@ -88,6 +91,27 @@ __device__ __forceinline__ void x_source_g(const GridBC& g, int gx, int& col, in
     }
 }
 
+// v mapped once around a periodic axis of n >= the halo depth: the column
+// of every halo value a fast tile (fast_tile) stages.
+__device__ __forceinline__ int wrap_once(int v, int n)
+{
+    return v < 0 ? v + n : (v >= n ? v - n : v);
+}
+
+// A tile of columns x0 .. x0+TXW-1 and rows y0 .. y0+R-1 stages without
+// boundary logic when it lies in the domain and so do the rows of its halo of
+// depth H, and its halo columns do too or lie at most one period away around
+// a periodic x axis. (Periodic x is the common case of a boundary strip:
+// handling it here keeps whole tile columns off the boundary path. Rows are
+// not wrapped: a per-row wrap costs scalar registers the kernels need.)
+__device__ __forceinline__ bool fast_tile(const GridBC& g, int x0, int y0, int TXW, int R, int H)
+{
+    const bool xok = x0 + TXW <= g.nx &&
+                     (g.bc[XLO] == PERIODIC ? g.nx >= H : (x0 >= H && x0 + TXW + H <= g.nx));
+    return xok && y0 >= H && y0 + R + H <= g.ny;
+}
+
+// bnd false: a fast tile; the halo lane's column is then its periodic image.
 template <int R, int H, bool ZG>
 __device__ __forceinline__ TileMapG tile_map_g(const GridBC& g, int x0, int y0, int lane, bool bnd)
 {
@@ -103,6 +127,9 @@ __device__ __forceinline__ TileMapG tile_map_g(const GridBC& g, int x0, int y0, 
     if (bnd) {
         x_source_g<ZG>(g, x0 + lane, t.mcol, t.mkind);
         if (hl && y0 + r < g.ny) x_source_g<ZG>(g, x0 + t.hlx, t.hcol, t.hkind);
+    } else {
+        // fast tile: the halo value's offset from the start of row y0
+        t.hcol = t.hrow * g.nx + wrap_once(x0 + t.hlx, g.nx);
     }
     return t;
 }
@@ -148,15 +175,15 @@ __device__ __forceinline__ void stage_load_g(const double* __restrict__ field, c
 {
     using S = StageG<R, H, PITCH>;
     if (!BND) {
+        // fast tile: rows in the domain, halo columns in it or one period away
         const unsigned ul = (unsigned)lane;
 #pragma unroll
         for (int r = 0; r < S::ROWS; ++r) {
             const double* row = field + i * plane + (int64_t)(y0 - H + r) * g.nx + x0;
             pre[r] = row[ul];
         }
-        // halo columns: offset from column x0 - H so that it is never negative
-        const double* hb = field + i * plane + (int64_t)y0 * g.nx + x0 - H;
-        pre[S::ROWS] = hb[(unsigned)(t.hrow * g.nx + t.hlx + H)];
+        const double* hb = field + i * plane + (int64_t)y0 * g.nx;
+        pre[S::ROWS] = hb[(unsigned)t.hcol];
     } else {
         const int64_t pi = i * plane, px = k.mirx[i] * plane, py = k.miry[i] * plane;
         const bool mout = t.mkind == CK_OUTLO || t.mkind == CK_OUTHI;

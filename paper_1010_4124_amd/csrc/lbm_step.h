@@ -329,8 +329,7 @@ __device__ __forceinline__ void step_work(const StepGrid& a, const Consts& k, SE
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
     const int x0 = tx * TX, y0 = ty * R;
     const int64_t plane = (int64_t)a.nx * a.ny;
-    const bool interior =
-        x0 >= HALO && x0 + TX + HALO <= a.nx && y0 >= HALO && y0 + R + HALO <= a.ny;
+    const bool interior = fast_tile(grid_bc(a), x0, y0, TX, R, HALO);
     const int gx = x0 + lane;
 
     // ---- phase 1: moments, equilibrium data, rest particle, diagnostics ----
