@@ -45,8 +45,11 @@ def build(verbose: bool = False) -> str:
     # stack and the optimiser forwards the loads to the argument segment only
     # if the copy has at most instcombine-max-copied-from-constant-users
     # users (default 300), so the limit is raised to keep every kernel free
-    # of that scratch copy.
-    flags = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+    # of that scratch copy. Floating-point contraction is off: every fused
+    # multiply-add is written out (__builtin_fma), so each kernel rounds as
+    # its source says and the kernels that share device code (single grid,
+    # batch, state pass) agree bit for bit.
+    flags = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
              "-mllvm", "-instcombine-max-copied-from-constant-users=100000",
              "-Wall", "-Wno-unused-result",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

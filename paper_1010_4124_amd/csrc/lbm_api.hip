@@ -94,6 +94,10 @@ void lbmi_fill_consts(const lbm_params* p, Consts* h)
         h->Fc[k] = b * c / den;
     }
     h->eps = p->weno_eps;
+    for (int i = 0; i < NV; ++i) {
+        h->epsx[i] = h->vx[i] != 0.0 ? p->weno_eps / (h->vx[i] * h->vx[i]) : 0.0;
+        h->epsy[i] = h->vy[i] != 0.0 ? p->weno_eps / (h->vy[i] * h->vy[i]) : 0.0;
+    }
 }
 
 int lbm_create(const lbm_params* p, lbm_ctx** out)

@@ -39,6 +39,8 @@ struct Consts {
     // Eqs. (44)-(46) with the constant denominator folded in.
     double Fa[3], Fb[3], Fc[3];
     double eps;             // WENO regulariser of Eq. (52)
+    double epsx[NV], epsy[NV];  // eps / v_ix^2 and eps / v_iy^2 (0 where v = 0):
+                                // the regulariser of WENO on f (weno_faces)
     double side_eq[4][NV];  // f^eq of each fixed-equilibrium side
     int mirx[NV], miry[NV]; // indices of (-vx, vy) and (vx, -vy)
 };
@@ -62,8 +64,8 @@ __device__ __forceinline__ CellEq cell_eq_from_sums(double r, double jx, double 
 {
     CellEq c;
     double ux = jx / r, uy = jy / r;
-    double u2 = ux * ux + uy * uy;
-    double T = E / r - 0.5 * u2;
+    double u2 = __builtin_fma(ux, ux, uy * uy);
+    double T = __builtin_fma(-0.5, u2, E / r);
     double iT = 1.0 / T;
     c.rho = r;
     c.T = T;
@@ -95,10 +97,16 @@ __device__ __forceinline__ double div_nr(double n, double d)
 }
 
 // WENO5-JS face fluxes along one strip of R cells (Sec. III.A, Eqs. (48)-(55)).
-// P[0..R+4] are the flux samples F = v f in upwind order (for v < 0 the
-// caller passes the line reversed: the paper's mirror image). hq[j],
-// j = 0..R, is the numerical flux at the face between upwind-ordered strip
-// cells j-1 and j, computed from P[j..j+4] = (F_{I-2}, ..., F_{I+2}).
+// P[0..R+4] are samples in upwind order (for v < 0 the caller passes the
+// line reversed: the paper's mirror image). hq[j], j = 0..R, is the
+// numerical flux at the face between upwind-ordered strip cells j-1 and j,
+// computed from P[j..j+4] = (P_{I-2}, ..., P_{I+2}).
+//
+// The paper's samples are F = v f. The kernels pass f itself with eps / v^2
+// in place of eps and scale the result by v: each smoothness indicator of
+// v f is v^2 times that of f, so eps + sigma_q(v f) = v^2 (eps / v^2 +
+// sigma_q(f)), the normalised weights are the same, and every candidate
+// flux is v times that of f. The two agree exactly in real arithmetic.
 //
 // The arithmetic is that of Eqs. (48)-(55) regrouped so that the first and
 // second differences of the samples are shared by the faces of the strip:
@@ -107,10 +115,13 @@ __device__ __forceinline__ double div_nr(double n, double d)
 //   eps + sigma_2 = E_{j+1} + ((g_{j+1} + g_{j+2}) / 2)^2,
 //   eps + sigma_3 = E_{j+2} + (D_{j+2} / 2 - g_{j+2})^2,   E_k = 13/12 D_k^2 + eps,
 // h^q = c + r_q with r_1 = 5/6 g_{j+1} - 1/3 g_j, r_2 = 1/6 g_{j+1} + 1/3 g_{j+2},
-// r_3 = 2/3 g_{j+2} - 1/6 g_{j+3}, and the weights delta_q / (eps+sigma_q)^2
-// scaled by prod_p (eps+sigma_p)^2 / delta_1, so that one division per face
-// remains. The differences are formed in a window that slides along the
-// strip, which keeps few values live at a time.
+// r_3 = 2/3 g_{j+2} - 1/6 g_{j+3}. With q_p = (eps + sigma_p)^2, the weights
+// delta_p / q_p, delta = (1, 6, 3) / 10, multiplied through by 10 q_1 q_2 q_3
+// leave one division per face:
+//   h = c + [q_2 q_3 r_1 + q_1 (q_3 s_2 + q_2 s_3)] / [q_2 q_3 + q_1 (6 q_3 + 3 q_2)],
+// s_2 = 6 r_2 = g_{j+1} + 2 g_{j+2}, s_3 = 3 r_3 = 2 g_{j+2} - g_{j+3} / 2.
+// The differences are formed in a window that slides along the strip, which
+// keeps few values live at a time.
 template <int R, class OnFace>
 __device__ __forceinline__ void weno_faces(const double (&P)[R + 5], double eps, OnFace&& on_face)
 {
@@ -132,13 +143,11 @@ __device__ __forceinline__ void weno_faces(const double (&P)[R + 5], double eps,
         q2 *= q2;
         q3 *= q3;
         const double W1 = q2 * q3;
-        const double W2 = 6.0 * (q1 * q3);
-        const double W3 = 3.0 * (q1 * q2);
         const double r1 = __builtin_fma(5.0 / 6.0, g1, -(1.0 / 3.0) * g0);
-        const double r2 = __builtin_fma(1.0 / 3.0, g2, (1.0 / 6.0) * g1);
-        const double r3 = __builtin_fma(2.0 / 3.0, g2, -(1.0 / 6.0) * g3);
-        const double num = __builtin_fma(W1, r1, __builtin_fma(W2, r2, W3 * r3));
-        const double den = W1 + W2 + W3;
+        const double s2 = __builtin_fma(2.0, g2, g1);
+        const double s3 = __builtin_fma(2.0, g2, -0.5 * g3);
+        const double num = __builtin_fma(q1, __builtin_fma(q3, s2, q2 * s3), W1 * r1);
+        const double den = __builtin_fma(q1, __builtin_fma(6.0, q3, 3.0 * q2), W1);
         on_face(j, P[j + 2] + div_nr(num, den));
         if (j < R) {
             g0 = g1;

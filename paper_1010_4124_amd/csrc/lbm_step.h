@@ -63,29 +63,28 @@ __device__ __forceinline__ GridBC grid_bc(const StepGrid& s)
 }
 
 // x pass: lane -> (row r = lane % R, strip s = lane / R); the flux
-// differences go to s_dx.
+// differences of f (WENO on f with eps / v_x^2: weno_faces) go to s_dx.
 template <int R, bool NEG>
-__device__ __forceinline__ void x_pass(const double* s_pl, double* s_dx, int lane, double v,
-                                       double eps)
+__device__ __forceinline__ void x_pass(const double* s_pl, double* s_dx, int lane, double eps)
 {
     const int r = lane % R, s = lane / R;
     const double* b = s_pl + (r + HALO) * PITCH + s * R;
     double P[R + 5];
 #pragma unroll
-    for (int k = 0; k < R + 5; ++k) P[k] = v * (NEG ? b[R + 5 - k] : b[k]);
+    for (int k = 0; k < R + 5; ++k) P[k] = NEG ? b[R + 5 - k] : b[k];
     double* out = s_dx + r * XPITCH + s * R;
     weno_strip<R, NEG>(P, eps, [&](int m, double d) { out[m] = d; });
 }
 
 // y pass: lane = column; calls upd(m, f_m, dh^y_m) for each cell of the strip
-// as soon as its two faces are known.
+// as soon as its two faces are known (flux differences of f, as in x_pass).
 template <int R, bool NEG, class Upd>
-__device__ __forceinline__ void y_pass(const double* s_pl, int lane, double v, double eps, Upd&& upd)
+__device__ __forceinline__ void y_pass(const double* s_pl, int lane, double eps, Upd&& upd)
 {
     const double* col = s_pl + lane + HALO;
     double P[R + 5];
 #pragma unroll
-    for (int k = 0; k < R + 5; ++k) P[k] = v * (NEG ? col[(R + 5 - k) * PITCH] : col[k * PITCH]);
+    for (int k = 0; k < R + 5; ++k) P[k] = NEG ? col[(R + 5 - k) * PITCH] : col[k * PITCH];
     // the centre value of cell m is re-read from LDS when the cell completes
     weno_strip<R, NEG>(P, eps, [&](int m, double d) { upd(m, col[(m + HALO) * PITCH], d); });
 }
@@ -183,7 +182,9 @@ __device__ __forceinline__ void plane_loop(const StepGrid& a, const Consts& k, S
     const GridBC g = grid_bc(a);
 
     // f' = f - cx dh^x - cy dh^y - ct (f - f^eq)
-    //    = (1 - ct) f + (ct rho F_k) poly(eta) - cx dh^x - cy dh^y
+    //    = (1 - ct) f + (ct rho F_k) poly(eta) - cx dh^x - cy dh^y,
+    // dh the face flux differences of F = v f, here (cx v_x) and (cy v_y)
+    // times those of f (weno_faces)
     auto compute = [&](int i) {
         const int ks = (i - 1) / 6;
         if (!LEAN && ks != kcur) {
@@ -191,11 +192,13 @@ __device__ __forceinline__ void plane_loop(const StepGrid& a, const Consts& k, S
 #pragma unroll
             for (int m = 0; m < (LEAN ? 1 : R); ++m) A[m] = (a.ct * rho[m]) * weight_c(k, ks, Tm[m]);
         }
-        const double vx = k.vx[i], vy = k.vy[i], eps = k.eps;
+        const double vx = k.vx[i], vy = k.vy[i];
+        // the faces are those of f; v goes into the Courant factors
+        const double cxv = a.cx * vx, cyv = a.cy * vy;
         if (vx < 0.0)
-            x_pass<R, true>(s_pl, s_dx, lane, vx, eps);
+            x_pass<R, true>(s_pl, s_dx, lane, k.epsx[i]);
         else
-            x_pass<R, false>(s_pl, s_dx, lane, vx, eps);
+            x_pass<R, false>(s_pl, s_dx, lane, k.epsx[i]);
         plane_sync<Waves<G, MODE>::N>();
         double* base = a.fout + i * plane + (int64_t)y0 * a.nx + x0;
         const double hv = k.hv2[i];
@@ -213,8 +216,8 @@ __device__ __forceinline__ void plane_loop(const StepGrid& a, const Consts& k, S
                 t0m = t0[m];
             }
             double fn = __builtin_fma(omct, fcm, Am * feq_poly(eta, t0m));
-            fn = __builtin_fma(-a.cx, dhx, fn);
-            fn = __builtin_fma(-a.cy, dhy, fn);
+            fn = __builtin_fma(-cxv, dhx, fn);
+            fn = __builtin_fma(-cyv, dhy, fn);
             if (CM) {
                 acc.r[m] += fn;
                 acc.jx[m] = __builtin_fma(fn, vx, acc.jx[m]);
@@ -230,9 +233,9 @@ __device__ __forceinline__ void plane_loop(const StepGrid& a, const Consts& k, S
             }
         };
         if (vy > 0.0) {
-            y_pass<R, false>(s_pl, lane, vy, eps, upd);
+            y_pass<R, false>(s_pl, lane, k.epsy[i], upd);
         } else if (vy < 0.0) {
-            y_pass<R, true>(s_pl, lane, vy, eps, upd);
+            y_pass<R, true>(s_pl, lane, k.epsy[i], upd);
         } else {
 #pragma unroll
             for (int m = 0; m < R; ++m) upd(m, s_pl[(m + HALO) * PITCH + lane + HALO], 0.0);
