@@ -30,6 +30,8 @@
 //            written for the next step.
 #pragma once
 
+#include <type_traits>
+
 #include "lbm_device.h"
 #include "lbm_stage.h"
 
@@ -157,14 +159,20 @@ struct Sums {
 // re-read) and consumed after the current plane's stores, so waiting for a
 // staged plane never waits for stores. With CM the sums of the new values
 // are accumulated into `acc`.
-template <int R, int G, bool BND, int DEPTH, bool NT, int MODE, class SE>
+//
+// late_load(tag) runs right after the first plane's loads are issued (tag: an
+// integral_constant, true on boundary tiles): the state
+// pass variants load the cell state there, so that staging the plane waits
+// only for the plane (vector memory operations complete in issue order) and
+// the x pass overlaps the state loads.
+template <int R, int G, bool BND, int DEPTH, bool NT, int MODE, class SE, class LateLoad>
 __device__ __forceinline__ void plane_loop(const StepGrid& a, const Consts& k, SE se,
                                            int grp, int x0, int y0, int lane, const TileMapG& t,
                                            int64_t plane, double* s_pl, double* s_dx,
                                            const double (&rho)[R], const double (&Tm)[R],
                                            const double (&uxt)[R], const double (&uyt)[R],
                                            const double (&t0)[MODE != PH_SUMS ? 1 : R],
-                                           Sums<R>& acc)
+                                           Sums<R>& acc, LateLoad&& late_load)
 {
     constexpr bool CM = MODE == PH_CARRY;     // accumulate the new moment sums
     constexpr bool LEAN = MODE != PH_SUMS;    // rho[] = dt/tau rho, no t0[], no A cache
@@ -244,6 +252,7 @@ __device__ __forceinline__ void plane_loop(const StepGrid& a, const Consts& k, S
 
     double pa[Stage<R>::NPRE], pb[Stage<R>::NPRE];
     stage_load_g<R, HALO, PITCH, BND, false>(a.fin, g, k, i0, x0, y0, lane, t, plane, pa);
+    late_load(std::integral_constant<bool, BND>{});
     stage_store_g<R, HALO, PITCH, BND, false>(g, k, se, i0, y0, lane, t, s_pl, pa);
     plane_sync<Waves<G, MODE>::N>();
     if constexpr (NPL == 1) {
@@ -341,17 +350,33 @@ __device__ __forceinline__ void step_work(const StepGrid& a, const Consts& k, SE
     Sums<R> acc;
 #pragma unroll
     for (int m = 0; m < R; ++m) acc.r[m] = acc.jx[m] = acc.jy[m] = acc.E[m] = 0.0;
-    if constexpr (PS) {
+    // PS: the cell state, loaded by plane_loop once the first plane's loads
+    // are in flight
+    auto load_state = [&](auto bnd) {
+        if constexpr (PS) {
+            // keep the scheduler from hoisting these above the plane's loads
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int m = 0; m < R; ++m) {
-            const bool act = gx < a.nx && y0 + m < a.ny;
-            const int64_t c = (int64_t)(y0 + m) * a.nx + gx;
-            rho[m] = act ? m_in[c] : a.ct;  // idle lanes: unit state
-            Tm[m] = act ? m_in[plane + c] : 1.0;
-            uxt[m] = act ? m_in[2 * plane + c] : 0.0;
-            uyt[m] = act ? m_in[3 * plane + c] : 0.0;
+            for (int m = 0; m < R; ++m) {
+                const int64_t c = (int64_t)(y0 + m) * a.nx + gx;
+                if constexpr (!decltype(bnd)::value) {
+                    // fast tile: every lane holds a cell; unconditional loads
+                    // keep the waits exact (no branch joins)
+                    rho[m] = m_in[c];
+                    Tm[m] = m_in[plane + c];
+                    uxt[m] = m_in[2 * plane + c];
+                    uyt[m] = m_in[3 * plane + c];
+                } else {
+                    const bool act = gx < a.nx && y0 + m < a.ny;
+                    rho[m] = act ? m_in[c] : a.ct;  // idle lanes: unit state
+                    Tm[m] = act ? m_in[plane + c] : 1.0;
+                    uxt[m] = act ? m_in[2 * plane + c] : 0.0;
+                    uyt[m] = act ? m_in[3 * plane + c] : 0.0;
+                }
+            }
         }
-    } else {
+    };
+    if constexpr (!PS) {
         Sums<R> sum;
         double fz[R];
 #pragma unroll
@@ -428,10 +453,10 @@ __device__ __forceinline__ void step_work(const StepGrid& a, const Consts& k, SE
     const TileMapG t = tile_map_g<R, HALO, false>(grid_bc(a), x0, y0, lane, !interior);
     if (interior)
         plane_loop<R, G, false, DEPTH, NT, MODE>(a, k, se, grp, x0, y0, lane, t, plane, s_pl,
-                                                 s_dx, rho, Tm, uxt, uyt, t0, acc);
+                                                 s_dx, rho, Tm, uxt, uyt, t0, acc, load_state);
     else
         plane_loop<R, G, true, DEPTH, NT, MODE>(a, k, se, grp, x0, y0, lane, t, plane, s_pl,
-                                                s_dx, rho, Tm, uxt, uyt, t0, acc);
+                                                s_dx, rho, Tm, uxt, uyt, t0, acc, load_state);
 
     // ---- phase 3: moment sums of f^{n+1} for the next step ----
     if (CM) {
