@@ -44,8 +44,11 @@ template <int R, int H, int PITCH>
 struct StageG {
     static constexpr int ROWS = R + 2 * H;
     static constexpr int NPRE = ROWS + 1;
-    static constexpr int PAD = ROWS * PITCH;  // 64 pad slots for idle halo lanes
-    static constexpr int SLOTS = PAD + 64;
+    // one pad slot per idle halo lane (lanes 2HR..63), which keeps the
+    // staged image within 8 KB per wave for R = 4
+    static constexpr int PAD = ROWS * PITCH;
+    static constexpr int NPAD = 64 - 2 * H * R > 0 ? 64 - 2 * H * R : 1;
+    static constexpr int SLOTS = PAD + NPAD;
     static_assert(2 * H * R <= 64, "the x-halo of the tile must fit one 64-lane load");
     static_assert(PITCH >= 64 + 2 * H, "row pitch too small");
 };
@@ -277,7 +280,8 @@ __device__ __forceinline__ void stage_store_g(const GridBC& g, const Consts& k, 
             : t.hkind == CK_CXHI ? se(k, XHI, i)
             : t.hkind == CK_NONE ? 0.0
                                  : h;
-    const int slot = lane < 2 * H * R ? (t.hrow + H) * PITCH + t.hlx + H : S::PAD + lane;
+    const int slot =
+        lane < 2 * H * R ? (t.hrow + H) * PITCH + t.hlx + H : S::PAD + (lane - 2 * H * R);
     s_pl[slot] = h;
 }
 

@@ -208,18 +208,38 @@ __device__ __forceinline__ void plane_loop(const StepGrid& a, const Consts& k, S
         else
             x_pass<R, false>(s_pl, s_dx, lane, k.epsx[i]);
         plane_sync<Waves<G, MODE>::N>();
+        // one velocity per wave (lean state): fold the four state values of
+        // each cell into the three the update needs, (dt/tau) rho F_k(T),
+        // 1 - |u|^2/2T and eta = v.u/T, before the y pass (fewer live
+        // registers there)
+        constexpr bool FOLD = LEAN && NPL == 1;
+        double fA[FOLD ? R : 1], ft0[FOLD ? R : 1], feta[FOLD ? R : 1];
+        if constexpr (FOLD) {
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                fA[m] = rho[m] * weight_c(k, ks, Tm[m]);
+                ft0[m] = __builtin_fma(-0.5 * Tm[m],
+                                       __builtin_fma(uxt[m], uxt[m], uyt[m] * uyt[m]), 1.0);
+                feta[m] = __builtin_fma(vx, uxt[m], vy * uyt[m]);
+            }
+        }
         double* base = a.fout + i * plane + (int64_t)y0 * a.nx + x0;
         const double hv = k.hv2[i];
         auto upd = [&](int m, double fcm, double dhy) {
             const double dhx = s_dx[m * XPITCH + lane];
-            const double eta = __builtin_fma(vx, uxt[m], vy * uyt[m]);
-            double Am, t0m;
-            if (LEAN) {
+            double eta, Am, t0m;
+            if constexpr (FOLD) {
+                eta = feta[m];
+                Am = fA[m];
+                t0m = ft0[m];
+            } else if (LEAN) {
+                eta = __builtin_fma(vx, uxt[m], vy * uyt[m]);
                 Am = rho[m] * weight_c(k, ks, Tm[m]);
                 // 1 - |u|^2 / 2T with u = T (u/T)
                 t0m = __builtin_fma(-0.5 * Tm[m],
                                     __builtin_fma(uxt[m], uxt[m], uyt[m] * uyt[m]), 1.0);
             } else {
+                eta = __builtin_fma(vx, uxt[m], vy * uyt[m]);
                 Am = A[m];
                 t0m = t0[m];
             }
