@@ -63,32 +63,107 @@ __device__ __forceinline__ double dweight_c(const Consts& k, int s, double T)
     return __builtin_fma(T, __builtin_fma(3.0 * T, k.Fa[s], 2.0 * k.Fb[s]), k.Fc[s]);
 }
 
+// Reverse mode of one WENO5 face given its shared differences (the same
+// function as weno_face_bar, Eqs. (48)-(55)): g[0..3] are the first
+// differences of the face's five samples, D[0..2] the second differences and
+// E[0..2] = 13/12 D^2 + eps. Returns in Gg[0..3] mu * dh/dg[k] (the centre
+// sample's own term, mu, is added by the caller). Fused multiply-adds
+// throughout and 1/sum(W) from the hardware reciprocal and one Newton step
+// (relative error near 2^-48).
+__device__ __forceinline__ void weno_face_bar_g(const double (&g)[4], const double (&D)[3],
+                                                const double (&E)[3], double mu, double (&Gg)[4])
+{
+    constexpr double C13 = 13.0 / 12.0;
+    const double b1 = __builtin_fma(0.5, D[0], g[1]);
+    const double b2 = 0.5 * (g[1] + g[2]);
+    const double b3 = __builtin_fma(0.5, D[2], -g[2]);
+    const double Q1 = __builtin_fma(b1, b1, E[0]);
+    const double Q2 = __builtin_fma(b2, b2, E[1]);
+    const double Q3 = __builtin_fma(b3, b3, E[2]);
+    const double q1 = Q1 * Q1, q2 = Q2 * Q2, q3 = Q3 * Q3;
+    const double W1 = q2 * q3, W2 = 6.0 * (q1 * q3), W3 = 3.0 * (q1 * q2);
+    const double r1 = __builtin_fma(5.0 / 6.0, g[1], -(1.0 / 3.0) * g[0]);
+    const double r2 = __builtin_fma(1.0 / 6.0, g[1], (1.0 / 3.0) * g[2]);
+    const double r3 = __builtin_fma(2.0 / 3.0, g[2], -(1.0 / 6.0) * g[3]);
+    const double S = W1 + W2 + W3;
+    const double r0 = __builtin_amdgcn_rcp(S);
+    const double iden = __builtin_fma(r0, __builtin_fma(-S, r0, 1.0), r0);
+    const double hq = __builtin_fma(W1, r1, __builtin_fma(W2, r2, W3 * r3)) * iden;  // h - c
+    // h = c + (sum W_q r_q) / (sum W_q)
+    const double mi = mu * iden;
+    const double r1b = mi * W1, r2b = mi * W2, r3b = mi * W3;
+    const double W1b = mi * (r1 - hq), W2b6 = 6.0 * (mi * (r2 - hq)),
+                 W3b3 = 3.0 * (mi * (r3 - hq));
+    // W1 = q2 q3, W2 = 6 q1 q3, W3 = 3 q1 q2
+    const double q1b = __builtin_fma(W2b6, q3, W3b3 * q2);
+    const double q2b = __builtin_fma(W1b, q3, W3b3 * q1);
+    const double q3b = __builtin_fma(W1b, q2, W2b6 * q1);
+    // q = Q^2, Q = b^2 + E: dQ = 2 Q dq, db = 2 b dQ, dD (from E) = 2 (13/12) D dQ
+    const double u1 = 4.0 * (Q1 * q1b), u2 = 4.0 * (Q2 * q2b), u3 = 4.0 * (Q3 * q3b);
+    const double b1b = b1 * u1, b2b = b2 * u2, b3b = b3 * u3;
+    // b1 = D0/2 + g1, b2 = (g1 + g2)/2, b3 = D2/2 - g2
+    const double D0b = __builtin_fma(C13 * D[0], u1, 0.5 * b1b);
+    const double D1b = (C13 * D[1]) * u2;
+    const double D2b = __builtin_fma(C13 * D[2], u3, 0.5 * b3b);
+    // r's and b's, then D_k = g_{k+1} - g_k
+    double g1b = __builtin_fma(0.5, b2b, b1b);
+    double g2b = __builtin_fma(0.5, b2b, -b3b);
+    g1b = __builtin_fma(5.0 / 6.0, r1b, __builtin_fma(1.0 / 6.0, r2b, g1b));
+    g2b = __builtin_fma(1.0 / 3.0, r2b, __builtin_fma(2.0 / 3.0, r3b, g2b));
+    Gg[0] = __builtin_fma(-1.0 / 3.0, r1b, -D0b);
+    Gg[1] = g1b + (D0b - D1b);
+    Gg[2] = g2b + (D1b - D2b);
+    Gg[3] = __builtin_fma(-1.0 / 6.0, r3b, D2b);
+}
+
 // Gather of one line strip: fw[0..R+7] are f at strip positions -4..R+3,
 // lw[0..R+5] are lambda' at positions -3..R+2; returns in acc[m] the sum over
 // the faces touching strip cell m of mu dh/df(m) (including the factor v).
+// The faces' first and second differences and E terms slide along the strip
+// as in the forward weno_faces.
 template <int R, bool NEG>
 __device__ __forceinline__ void gather_strip(const double (&fw)[R + 8], const double (&lw)[R + 6],
                                              double v, double cn, double eps, double (&acc)[R])
 {
+    constexpr double C13 = 13.0 / 12.0;
     double Pw[R + 8];
 #pragma unroll
     for (int q = 0; q < R + 8; ++q) Pw[q] = v * (NEG ? fw[R + 7 - q] : fw[q]);
+    // dL/dP at the R+8 upwind-ordered positions
+    double Gp[R + 8];
 #pragma unroll
-    for (int m = 0; m < R; ++m) acc[m] = 0.0;
+    for (int q = 0; q < R + 8; ++q) Gp[q] = 0.0;
+    double g[4] = {Pw[1] - Pw[0], Pw[2] - Pw[1], Pw[3] - Pw[2], Pw[4] - Pw[3]};
+    double D[3] = {g[1] - g[0], g[2] - g[1], g[3] - g[2]};
+    double E[3] = {__builtin_fma(C13 * D[0], D[0], eps), __builtin_fma(C13 * D[1], D[1], eps),
+                   __builtin_fma(C13 * D[2], D[2], eps)};
 #pragma unroll
     for (int t = 0; t < R + 4; ++t) {
         // face between strip positions I and I+1: I = t-2 (v >= 0) or R-t (v < 0)
         const double mu = NEG ? cn * (lw[R + 4 - t] - lw[R + 3 - t]) : cn * (lw[t + 2] - lw[t + 1]);
-        double G[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        weno_face_bar(&Pw[t], eps, mu, G);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            const int m = NEG ? R + 3 - t - q : t + q - 4;
-            if (m >= 0 && m < R) acc[m] += G[q];
+        double Gg[4];
+        weno_face_bar_g(g, D, E, mu, Gg);
+        // g_k = P_{t+k+1} - P_{t+k}; the centre sample P_{t+2} adds mu
+        Gp[t] -= Gg[0];
+        Gp[t + 1] += Gg[0] - Gg[1];
+        Gp[t + 2] += (Gg[1] - Gg[2]) + mu;
+        Gp[t + 3] += Gg[2] - Gg[3];
+        Gp[t + 4] += Gg[3];
+        if (t + 1 < R + 4) {
+            g[0] = g[1];
+            g[1] = g[2];
+            g[2] = g[3];
+            g[3] = Pw[t + 5] - Pw[t + 4];
+            D[0] = D[1];
+            D[1] = D[2];
+            D[2] = g[3] - g[2];
+            E[0] = E[1];
+            E[1] = E[2];
+            E[2] = __builtin_fma(C13 * D[2], D[2], eps);
         }
     }
 #pragma unroll
-    for (int m = 0; m < R; ++m) acc[m] *= v;
+    for (int m = 0; m < R; ++m) acc[m] = v * Gp[NEG ? R + 3 - m : m + 4];
 }
 
 // Value of plane i at (gx, gy) with the forward ghost rules (domain or the
