@@ -31,7 +31,7 @@ template <int R, int G, int W, int DEPTH, bool NT, int MODE>
 __global__ __launch_bounds__((64 * Waves<G, MODE>::N)) __attribute__((amdgpu_waves_per_eu(W)))
 void k_step(StepArgs a)
 {
-    __shared__ double lds[Waves<G, MODE>::N * WaveLds<R>::SIZE];
+    __shared__ double lds[Waves<G, MODE>::N * WaveLds<R, MODE>::SIZE];
 
     const int b = blockIdx.x;
     const int work = (b & 7) * a.per_xcd + (b >> 3);

@@ -104,13 +104,14 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// Per-wave LDS region: the staged plane, the x flux differences, and (reused)
-// the exchange of the 4 x R moment sums of the wave's lanes.
-template <int R>
+// Per-wave LDS region: the staged plane, the x flux differences, and (reused,
+// carried-moment mode only) the exchange of the 4 x R moment sums of the
+// wave's lanes.
+template <int R, int MODE>
 struct WaveLds {
     static constexpr int DX = Stage<R>::SLOTS;
     static constexpr int WORK = Stage<R>::SLOTS + R * XPITCH;
-    static constexpr int XCH = 4 * R * 64;
+    static constexpr int XCH = MODE == 1 ? 4 * R * 64 : 0;
     static constexpr int SIZE = WORK > XCH ? WORK : XCH;
 };
 
@@ -306,7 +307,7 @@ __device__ __forceinline__ void plane_loop(const StepGrid& a, const Consts& k, S
 template <int R, int G>
 __device__ __forceinline__ void exchange_sums(double* lds, int wave, int lane, Sums<R>& s, bool all)
 {
-    double* mine = lds + wave * WaveLds<R>::SIZE;
+    double* mine = lds + wave * WaveLds<R, 1>::SIZE;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         mine[(0 * R + m) * 64 + lane] = s.r[m];
@@ -323,7 +324,7 @@ __device__ __forceinline__ void exchange_sums(double* lds, int wave, int lane, S
             double jy = p0[(2 * R + m) * 64 + lane], E = p0[(3 * R + m) * 64 + lane];
 #pragma unroll
             for (int w = 1; w < G; ++w) {
-                const double* p = lds + w * WaveLds<R>::SIZE;
+                const double* p = lds + w * WaveLds<R, 1>::SIZE;
                 r += p[(0 * R + m) * 64 + lane];
                 jx += p[(1 * R + m) * 64 + lane];
                 jy += p[(2 * R + m) * 64 + lane];
@@ -344,7 +345,7 @@ __device__ __forceinline__ void exchange_sums(double* lds, int wave, int lane, S
 // m_in / m_out: PH_CARRY reads and writes the moment sums (rho, j_x, j_y, E,
 // each [ny][nx]); PH_STATE reads the cell state (dt/tau rho, T, u/T, v/T)
 // and leaves the rest particle and the diagnostics to the state pass. lds
-// holds Waves<G, MODE>::N regions of WaveLds<R>::SIZE doubles.
+// holds Waves<G, MODE>::N regions of WaveLds<R, MODE>::SIZE doubles.
 template <int R, int G, int DEPTH, bool NT, int MODE, class SE>
 __device__ __forceinline__ void step_work(const StepGrid& a, const Consts& k, SE se, int tile,
                                           int grp, double* ke_dst, double* lds,
@@ -356,8 +357,8 @@ __device__ __forceinline__ void step_work(const StepGrid& a, const Consts& k, SE
     const int lane = threadIdx.x & 63;
     const int wave = NW > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
     if (NW > 1) grp = wave;
-    double* s_pl = lds + wave * WaveLds<R>::SIZE;
-    double* s_dx = s_pl + WaveLds<R>::DX;
+    double* s_pl = lds + wave * WaveLds<R, MODE>::SIZE;
+    double* s_dx = s_pl + WaveLds<R, MODE>::DX;
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
     const int x0 = tx * TX, y0 = ty * R;
     const int64_t plane = (int64_t)a.nx * a.ny;
