@@ -53,6 +53,12 @@ CASES = {
     "outflow-walls-fixed-tiny": lambda: generic(5, 7, (O, R, F, O), 17),
     "paper-shear-layer": lambda: inputs.khi_paper(130, 64, dx=2e-3, dy=2e-3, dt=2e-5,
                                                   tau=2e-5, Dv=8e-3, Drho=1.6e-2),
+    # widths of whole tiles (no ragged x tail) with ragged y
+    "periodic-128x45": lambda: generic(128, 45, (P, P, P, P), 18),
+    "khi-walls-y-256x37": lambda: inputs.khi(256, 37, dx=1e-3, dy=1e-3, dt=1e-5, tau=1e-5,
+                                             Dv=0.01, Drho=0.01, pert=1e-2),
+    "fixed-x-walls-y-64x22": lambda: generic(64, 22, (F, F, R, R), 19),
+    "outflow-x-128x41": lambda: generic(128, 41, (O, O, P, P), 20),
 }
 
 
