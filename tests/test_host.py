@@ -1,0 +1,138 @@
+"""Host-side logic, no GPU: the tuner's tie rule, the benchmark's hash-guarded
+traffic figure, the seeded input recipes and the stabilisation loop (on a
+problem with a known minimum)."""
+import math
+
+import numpy as np
+import pytest
+
+import bench
+from paper_1010_4124_amd import inputs, stabilize, tune
+
+
+# --- tuner ---------------------------------------------------------------------
+def test_tie_rule_picks_lowest_index_within_band():
+    # 3 is fastest; 5 is within 1.5% of it and 0 is not: 3 wins
+    assert tune._pick({0: 1.02, 3: 1.0, 5: 1.005, 7: 1.2}) == 3
+    # 2 is within the band of 4: the lower index wins
+    assert tune._pick({4: 1.0, 2: 1.01}) == 2
+    # (variant, slots) pairs order lexicographically
+    assert tune._pick({(1, 0): 1.0, (0, 64): 1.01, (0, 0): 1.2}) == (0, 64)
+    assert tune.TIE == pytest.approx(0.015)
+
+
+# --- benchmark traffic figure --------------------------------------------------
+def _summary(tmp_path, sha, kernel, traffic):
+    p = tmp_path / "summary.md"
+    p.write_text(f"kernel: {kernel}\nsource_sha1: {sha}\n"
+                 f"traffic_bytes_per_launch: {traffic}\n")
+    return str(p)
+
+
+def test_traffic_needs_matching_sources_and_kernel(tmp_path, monkeypatch):
+    k = "lbmd::k_step<4, 18, 4, 1, false, 2> + lbmd::k_state"
+    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", _summary(tmp_path, bench.source_hash(), k,
+                                                           "1.25e+08"))
+    assert bench.read_traffic(k) == 1.25e8
+    assert bench.read_traffic("lbmd::k_step<4, 1, 3, 1, false, 0>") is None
+    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", _summary(tmp_path, "0123456789abcdef", k,
+                                                           "1.25e+08"))
+    assert bench.read_traffic(k) is None  # counters taken on other sources
+    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(tmp_path / "missing.md"))
+    assert bench.read_traffic(k) is None
+
+
+def test_source_hash_covers_the_kernel_sources():
+    h = bench.source_hash()
+    assert isinstance(h, str) and len(h) >= 16 and h == bench.source_hash()
+
+
+# --- inputs --------------------------------------------------------------------
+def test_batch_draw_is_seeded_and_in_range():
+    a, b = inputs.batch_draw(2024, n=64), inputs.batch_draw(2024, n=64)
+    assert a == b and len(a) == 64
+    assert inputs.batch_draw(2025, n=64) != a
+    for d in a:
+        assert d["nx"] in (128, 192, 256, 384, 512) and d["ny"] in (128, 192, 256, 384, 512)
+        assert 0.005 <= d["Dv"] <= 0.08 and 0.005 <= d["Drho"] <= 0.08
+    # both widths log-uniform: their logs spread over most of the range
+    lv = np.log([d["Dv"] for d in a])
+    assert lv.max() - lv.min() > 0.7 * (math.log(0.08) - math.log(0.005))
+
+
+def test_shear_layer_fields():
+    s = inputs.khi(64, 48, Dv=0.01, Drho=0.02)
+    r, ux, uy, T = s.fields()
+    assert r.shape == ux.shape == uy.shape == T.shape == (48, 64)
+    # mirror symmetry about y = 0 of the cell centres (to rounding of the
+    # centres): ux odd, rho + mirror = rho1 + rho2
+    assert np.allclose(ux[::-1], -ux, rtol=0, atol=1e-13)
+    assert np.allclose(r + r[::-1], 7.0, rtol=0, atol=1e-14)
+    assert np.allclose(r * T, 2.5, rtol=1e-15, atol=0)  # uniform pressure
+    assert s.bc == (inputs.PERIODIC, inputs.PERIODIC, inputs.REFLECT, inputs.REFLECT)
+    assert abs(uy).max() <= 1e-3 + 1e-18
+
+
+def test_paper_shear_layer_fields():
+    s = inputs.khi_paper(60, 20)
+    r, ux, uy, T = s.fields()
+    # interface normal to x: the flow along y is odd in x, the perturbation even
+    assert np.allclose(uy + uy[:, ::-1], 0.0, rtol=0, atol=1e-13)
+    assert np.allclose(ux, ux[:, ::-1], rtol=0, atol=1e-15)
+    assert np.allclose(r + r[:, ::-1], 7.0, rtol=0, atol=1e-14)
+    assert s.bc[:2] == (inputs.OUTFLOW, inputs.OUTFLOW) and s.ke_axis == 1
+
+
+def test_sod_states():
+    s = inputs.sod()
+    r, ux, uy, T = s.fields()
+    x = (np.arange(s.nx) + 0.5) * s.dx
+    left = x <= 0.5
+    assert np.all(r[:, left] == 1.0) and np.all(r[:, ~left] == 0.125)
+    assert np.allclose((r * T)[:, left], 1.0) and np.allclose((r * T)[:, ~left], 0.1)
+    assert not ux.any() and not uy.any()
+
+
+def test_mode_basis_is_orthogonal():
+    A, labels = inputs.mode_basis(32, 1e-3)
+    G = A @ A.T
+    assert np.allclose(G - np.diag(np.diag(G)), 0.0, atol=1e-12)
+    assert G[0, 0] == pytest.approx(32) and np.allclose(np.diag(G)[1:-1], 16)
+    assert labels[0] == ("cos", 0) and labels[-1] == ("sin", 16)
+
+
+# --- stabilisation loop ---------------------------------------------------------
+class _Bowl:
+    """J = 1 + (ln Dv - ln 0.04)^2 + 2 (ln Drho - ln 0.03)^2: minimum at
+    (0.04, 0.03), inside the default bounds."""
+
+    def run(self, Dv, Drho, amps, keep_checkpoints=True):
+        return 1.0 + (math.log(Dv / 0.04)) ** 2 + 2.0 * (math.log(Drho / 0.03)) ** 2, None
+
+    def gradient(self, Dv, Drho, amps, ck=None):
+        return (2.0 * math.log(Dv / 0.04) / Dv, 4.0 * math.log(Drho / 0.03) / Drho, None)
+
+
+def test_stabilize_descends_monotonically_within_bounds():
+    hist = stabilize.stabilize(_Bowl(), 0.01, 0.01, np.zeros(4), iters=12)
+    J = [h["J"] for h in hist]
+    assert all(b <= a for a, b in zip(J, J[1:]))
+    for h in hist:
+        assert 0.005 <= h["Dv"] <= 0.08 and 0.005 <= h["Drho"] <= 0.08
+    assert J[-1] < 1.0 + 1e-3 * (J[0] - 1.0)
+    assert hist[-1]["Dv"] == pytest.approx(0.04, rel=0.05)
+    assert hist[-1]["Drho"] == pytest.approx(0.03, rel=0.05)
+
+
+def test_stabilize_stops_at_a_bound():
+    class Edge(_Bowl):
+        # minimum beyond the upper bound in Dv: the iterate must stay on it
+        def run(self, Dv, Drho, amps, keep_checkpoints=True):
+            return 1.0 + (math.log(Dv / 0.5)) ** 2 + (math.log(Drho / 0.03)) ** 2, None
+
+        def gradient(self, Dv, Drho, amps, ck=None):
+            return (2.0 * math.log(Dv / 0.5) / Dv, 2.0 * math.log(Drho / 0.03) / Drho, None)
+
+    hist = stabilize.stabilize(Edge(), 0.02, 0.01, np.zeros(4), iters=10)
+    assert hist[-1]["Dv"] == pytest.approx(0.08)
+    assert all(b["J"] <= a["J"] for a, b in zip(hist, hist[1:]))
