@@ -45,7 +45,8 @@ BYTES_PER_LUP = 19 * 8 * 2          # forward: f^n read once, f^{n+1} written on
 ADJ_BYTES_PER_LUP = 19 * 8 * 3      # adjoint: f^n and lambda^{n+1} read, lambda^n written
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 512 << 20              # reference copy for the counter scale factors
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_khi512_counters.md")
+# counter summaries of the 512^2 step, one per profiled variant
+TRAFFIC_SUMMARIES = os.path.join(ROOT, "profiles", "k_step_*_khi512_counters.md")
 METRIC = "MLUPS (D2V19+WENO5, FP64) fwd/adjoint/batched + % HBM roofline"
 
 
@@ -83,21 +84,21 @@ def sync_time(fn):
     return e0.elapsed_time(e1) / 1e3, time.perf_counter() - w0
 
 
-def read_traffic(kernel_name):
-    """HBM bytes per launch from the committed counter summary, or None when
-    it is missing, was taken on other sources, or on another kernel."""
-    try:
-        txt = open(TRAFFIC_SUMMARY).read()
-    except OSError:
-        return None
-    m_hash = re.search(r"source_sha1:\s*(\w+)", txt)
-    m_kern = re.search(r"kernel:\s*(.+)", txt)
-    m_traf = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not (m_hash and m_kern and m_traf):
-        return None
-    if m_hash.group(1) != source_hash() or m_kern.group(1).strip() != kernel_name:
-        return None
-    return float(m_traf.group(1))
+def read_traffic(kernel_name, pattern=None):
+    """HBM bytes per launch from the committed counter summary of this kernel,
+    or None when there is none taken on the current sources."""
+    for path in sorted(glob.glob(pattern or TRAFFIC_SUMMARIES)):
+        try:
+            txt = open(path).read()
+        except OSError:
+            continue
+        m_hash = re.search(r"source_sha1:\s*(\w+)", txt)
+        m_kern = re.search(r"kernel:\s*(.+)", txt)
+        m_traf = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+        if (m_hash and m_kern and m_traf and m_hash.group(1) == source_hash()
+                and m_kern.group(1).strip() == kernel_name):
+            return float(m_traf.group(1))
+    return None
 
 
 def step_kernel_name(variant):

@@ -22,24 +22,25 @@ def test_tie_rule_picks_lowest_index_within_band():
 
 
 # --- benchmark traffic figure --------------------------------------------------
-def _summary(tmp_path, sha, kernel, traffic):
-    p = tmp_path / "summary.md"
+def _summary(tmp_path, name, sha, kernel, traffic):
+    p = tmp_path / name
     p.write_text(f"kernel: {kernel}\nsource_sha1: {sha}\n"
                  f"traffic_bytes_per_launch: {traffic}\n")
-    return str(p)
 
 
-def test_traffic_needs_matching_sources_and_kernel(tmp_path, monkeypatch):
-    k = "lbmd::k_step<4, 18, 4, 1, false, 2> + lbmd::k_state"
-    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", _summary(tmp_path, bench.source_hash(), k,
-                                                           "1.25e+08"))
-    assert bench.read_traffic(k) == 1.25e8
-    assert bench.read_traffic("lbmd::k_step<4, 1, 3, 1, false, 0>") is None
-    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", _summary(tmp_path, "0123456789abcdef", k,
-                                                           "1.25e+08"))
-    assert bench.read_traffic(k) is None  # counters taken on other sources
-    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(tmp_path / "missing.md"))
-    assert bench.read_traffic(k) is None
+def test_traffic_needs_matching_sources_and_kernel(tmp_path):
+    k1 = "lbmd::k_step<4, 18, 4, 1, false, 2> + lbmd::k_state"
+    k2 = "lbmd::k_step<8, 18, 3, 1, false, 2> + lbmd::k_state"
+    pat = str(tmp_path / "k_step_*_counters.md")
+    assert bench.read_traffic(k1, pat) is None  # no summaries
+    _summary(tmp_path, "k_step_a_counters.md", bench.source_hash(), k1, "1.25e+08")
+    _summary(tmp_path, "k_step_b_counters.md", bench.source_hash(), k2, "1.5e+08")
+    assert bench.read_traffic(k1, pat) == 1.25e8
+    assert bench.read_traffic(k2, pat) == 1.5e8
+    assert bench.read_traffic("lbmd::k_step<4, 1, 3, 1, false, 0>", pat) is None
+    # counters taken on other sources do not count
+    _summary(tmp_path, "k_step_b_counters.md", "0123456789abcdef", k2, "1.5e+08")
+    assert bench.read_traffic(k2, pat) is None
 
 
 def test_source_hash_covers_the_kernel_sources():
