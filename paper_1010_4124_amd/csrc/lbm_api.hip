@@ -16,24 +16,36 @@ using namespace lbmd;
 namespace {
 thread_local std::string g_err;
 
+// Stores the message of the calling thread's last failure; never throws (on
+// a host allocation failure the previous message stays).
+void set_error(const char* msg) noexcept
+{
+    try {
+        g_err = msg;
+    } catch (...) {
+    }
+}
+
 int fail(int code, const char* fmt, const char* a = "", long long b = 0)
 {
     char buf[512];
     std::snprintf(buf, sizeof(buf), fmt, a, b);
-    g_err = buf;
+    set_error(buf);
     return code;
 }
 
 int hip_fail(hipError_t e, const char* where)
 {
-    g_err = std::string(where) + ": " + hipGetErrorString(e);
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), "%s: %s", where, hipGetErrorString(e));
+    set_error(buf);
     return LBM_EHIP;
 }
 }  // namespace
 
 const char* lbm_last_error(void) { return g_err.c_str(); }
 
-void lbmi_set_error(const char* msg) { g_err = msg; }
+void lbmi_set_error(const char* msg) { set_error(msg); }
 
 const char* lbm_version(void) { return "lbm_hip 0.1 gfx950 d2v19-weno5"; }
 
@@ -133,7 +145,7 @@ int lbm_create(const lbm_params* p, lbm_ctx** out)
         (e = hipMalloc(&c->gbuf, NV * 2 * ((size_t)p->nx + p->ny) * sizeof(double))) !=
             hipSuccess) {
         lbm_destroy(c);
-        g_err = std::string("hipMalloc: ") + hipGetErrorString(e);
+        hip_fail(e, "hipMalloc");
         return LBM_ENOMEM;
     }
     {

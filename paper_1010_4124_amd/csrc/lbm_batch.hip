@@ -20,7 +20,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
-#include <string>
+#include <new>
 #include <vector>
 
 #include "lbm.h"
@@ -186,14 +186,32 @@ struct lbm_batch {
 };
 
 namespace {
-int bfail(int code, const std::string& msg)
+int bfail(int code, const char* msg)
 {
-    lbmi_set_error(msg.c_str());
+    lbmi_set_error(msg);
     return code;
 }
 int bhip(hipError_t e, const char* where)
 {
-    return bfail(LBM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), "%s: %s", where, hipGetErrorString(e));
+    return bfail(LBM_EHIP, buf);
+}
+
+// Entry points that use host containers turn an allocation failure into
+// LBM_ENOMEM: no C++ exception crosses the C interface.
+template <class F>
+int guarded(F&& f) noexcept
+{
+    try {
+        return f();
+    } catch (const std::bad_alloc&) {
+        lbmi_set_error("host allocation failed");
+        return LBM_ENOMEM;
+    } catch (...) {
+        lbmi_set_error("unexpected host exception");
+        return LBM_EHIP;
+    }
 }
 
 void drop_graphs(lbm_batch* b)
@@ -358,7 +376,8 @@ int get_graph(lbm_batch* b, const double* x, double* y, bool ke, hipGraphExec_t*
 
 extern "C" {
 
-int lbm_batch_create(const lbm_params* inst, int32_t n, const int64_t* f_offset, lbm_batch** out)
+static int batch_create_impl(const lbm_params* inst, int32_t n, const int64_t* f_offset,
+                             lbm_batch** out)
 {
     if (!out) return bfail(LBM_EINVAL, "out is null");
     *out = nullptr;
@@ -444,7 +463,8 @@ int lbm_batch_create(const lbm_params* inst, int32_t n, const int64_t* f_offset,
             hipSuccess ||
         (e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess) {
         lbm_batch_destroy(b);
-        return bfail(LBM_ENOMEM, std::string("batch allocation: ") + hipGetErrorString(e));
+        bhip(e, "batch allocation");
+        return LBM_ENOMEM;
     }
     int64_t goff = 0;
     for (int i = 0; i < n; ++i) {
@@ -547,8 +567,8 @@ int lbm_batch_moments(lbm_batch* b, const double* f, double* rho, double* ux, do
     return LBM_OK;
 }
 
-int lbm_batch_step(lbm_batch* b, const double* f_in, double* f_out, int32_t nsteps,
-                   double* ke_log, lbm_stream stream)
+static int batch_step_impl(lbm_batch* b, const double* f_in, double* f_out, int32_t nsteps,
+                           double* ke_log, lbm_stream stream)
 {
     if (!b || !f_in || !f_out) return bfail(LBM_EINVAL, "null argument");
     if (nsteps < 1) return bfail(LBM_EINVAL, "nsteps must be >= 1");
@@ -604,7 +624,7 @@ int lbm_batch_step(lbm_batch* b, const double* f_in, double* f_out, int32_t nste
     return LBM_OK;
 }
 
-int lbm_batch_set_step_variant(lbm_batch* b, int32_t v)
+static int batch_set_variant_impl(lbm_batch* b, int32_t v)
 {
     if (!b || v < 0 || v >= step_variant_count()) return bfail(LBM_EINVAL, "bad variant");
     if (v == b->variant) return LBM_OK;
@@ -646,9 +666,9 @@ int lbm_batch_get_schedule(lbm_batch* b, int32_t* out2)
 
 }  // extern "C"
 
-extern "C" int lbm_batch_tune(lbm_batch* b, const double* f_in, double* f_tmp, int32_t nsteps,
-                              const int32_t* variants, int32_t nv, const int32_t* slots,
-                              int32_t ns, double* ms_out, lbm_stream stream)
+static int batch_tune_impl(lbm_batch* b, const double* f_in, double* f_tmp, int32_t nsteps,
+                           const int32_t* variants, int32_t nv, const int32_t* slots, int32_t ns,
+                           double* ms_out, lbm_stream stream)
 {
     if (!b || !f_in || !f_tmp || nsteps < 1 || nv < 0 || ns < 0 || (nv > 0 && !variants) ||
         (ns > 0 && !slots))
@@ -706,3 +726,33 @@ extern "C" int lbm_batch_tune(lbm_batch* b, const double* f_in, double* f_tmp, i
     hipEventDestroy(e1);
     return rc;
 }
+
+// The C entry points of the allocating calls, behind the exception guard.
+extern "C" {
+
+int lbm_batch_create(const lbm_params* inst, int32_t n, const int64_t* f_offset, lbm_batch** out)
+{
+    return guarded([&] { return batch_create_impl(inst, n, f_offset, out); });
+}
+
+int lbm_batch_step(lbm_batch* b, const double* f_in, double* f_out, int32_t nsteps,
+                   double* ke_log, lbm_stream stream)
+{
+    return guarded([&] { return batch_step_impl(b, f_in, f_out, nsteps, ke_log, stream); });
+}
+
+int lbm_batch_set_step_variant(lbm_batch* b, int32_t v)
+{
+    return guarded([&] { return batch_set_variant_impl(b, v); });
+}
+
+int lbm_batch_tune(lbm_batch* b, const double* f_in, double* f_tmp, int32_t nsteps,
+                   const int32_t* variants, int32_t nv, const int32_t* slots, int32_t ns,
+                   double* ms_out, lbm_stream stream)
+{
+    return guarded([&] {
+        return batch_tune_impl(b, f_in, f_tmp, nsteps, variants, nv, slots, ns, ms_out, stream);
+    });
+}
+
+}  // extern "C"
