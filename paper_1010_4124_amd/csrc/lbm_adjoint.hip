@@ -166,6 +166,110 @@ __device__ __forceinline__ void gather_strip(const double (&fw)[R + 8], const do
     for (int m = 0; m < R; ++m) acc[m] = v * Gp[NEG ? R + 3 - m : m + 4];
 }
 
+// x gather of a whole tile row, R >= 4, each face computed once. Seen from
+// the upwind side (the mirrored row for v < 0: the "canonical" frame), a
+// lane's strip of R cells owns the R faces between its positions t-2 and t-1,
+// t = 0..R-1; their gradient reaches cells t-4..t, so every face feeds the
+// owning strip and the 4 cells at the end of the strip before it. Those 4
+// sums go through LDS (xl: 4 per lane) to that strip. The strip at the end
+// of the row gets the same from the 4 faces of the strip beyond the tile,
+// which lanes 0..4R-1 compute (one face each, xe: R x 4 x 4). A lane thus
+// evaluates R + 1 faces instead of the R + 4 of gather_strip. Returns the
+// sum over faces of mu dh/df for the lane's R cells (factor v included), in
+// natural cell order, like gather_strip.
+template <int R, bool NEG>
+__device__ __forceinline__ void gather_x_row(const double* s_f, const double* s_l, double* xl,
+                                             double* xe, int lane, double v, double cn,
+                                             double eps, double (&acc)[R])
+{
+    static_assert(R >= 4 && 64 % R == 0, "a strip's neighbour covers the 4 cells a face reaches");
+    constexpr double C13 = 13.0 / 12.0;
+    constexpr int NS = 64 / R;
+    const int r = lane % R, s = lane / R;
+    const double cnc = NEG ? -cn : cn;  // mu = cnc (lambda_c(I+1) - lambda_c(I))
+    // canonical position p of this strip <-> LDS column of row r
+    const double* fr = s_f + (r + FH) * AP + FH;
+    const double* lr = s_l + (r + LH) * AP + LH;
+    auto col = [&](int p) { return NEG ? s * R + R - 1 - p : s * R + p; };
+    double P[R + 4];  // v f at canonical positions -4..R-1
+#pragma unroll
+    for (int k = 0; k < R + 4; ++k) P[k] = v * fr[col(k - 4)];
+    double Ac[R], LG[4];
+#pragma unroll
+    for (int m = 0; m < R; ++m) Ac[m] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) LG[k] = 0.0;
+    double g[4] = {P[1] - P[0], P[2] - P[1], P[3] - P[2], P[4] - P[3]};
+    double D[3] = {g[1] - g[0], g[2] - g[1], g[3] - g[2]};
+    double E[3] = {__builtin_fma(C13 * D[0], D[0], eps), __builtin_fma(C13 * D[1], D[1], eps),
+                   __builtin_fma(C13 * D[2], D[2], eps)};
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const double mu = cnc * (lr[col(t - 1)] - lr[col(t - 2)]);
+        double Gg[4];
+        weno_face_bar_g(g, D, E, mu, Gg);
+        const double G[5] = {-Gg[0], Gg[0] - Gg[1], (Gg[1] - Gg[2]) + mu, Gg[2] - Gg[3], Gg[3]};
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const int d = t + q - 4;  // canonical cell of sample q
+            if (d >= 0)
+                Ac[d] += G[q];
+            else
+                LG[d + 4] += G[q];
+        }
+        if (t + 1 < R) {
+            g[0] = g[1];
+            g[1] = g[2];
+            g[2] = g[3];
+            g[3] = P[t + 5] - P[t + 4];
+            D[0] = D[1];
+            D[1] = D[2];
+            D[2] = g[3] - g[2];
+            E[0] = E[1];
+            E[1] = E[2];
+            E[2] = __builtin_fma(C13 * D[2], D[2], eps);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xl[4 * lane + k] = LG[k];
+    // the 4 faces beyond each row's last canonical strip (positions R-2+u
+    // and R-1+u of that strip, u = 0..3): lane 4 er + u for row er
+    if (lane < 4 * R) {
+        const int er = lane >> 2, u = lane & 3;
+        const double* fe = s_f + (er + FH) * AP + FH;
+        const double* le = s_l + (er + LH) * AP + LH;
+        // canonical position p of the row's last canonical strip <-> column
+        auto ecol = [&](int p) { return NEG ? R - 1 - p : (NS - 1) * R + p; };
+        double Pe[5], Ge[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 5; ++q) Pe[q] = v * fe[ecol(R + u - 4 + q)];
+        const double mu = cnc * (le[ecol(R + u - 1)] - le[ecol(R + u - 2)]);
+        weno_face_bar(Pe, eps, mu, Ge);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xe[16 * er + 4 * u + q] = q < 4 - u ? Ge[q] : 0.0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const int S = NEG ? NS - 1 - s : s;  // canonical strip index
+    if (S < NS - 1) {
+        const int nb = NEG ? lane - R : lane + R;  // canonical next strip, same row
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Ac[R - 4 + k] += xl[4 * nb + k];
+    } else {
+        // face u reaches cell R-4+u+q of this strip for q < 4-u
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            double sum = 0.0;
+#pragma unroll
+            for (int u = 0; u <= k; ++u) sum += xe[16 * r + 4 * u + (k - u)];
+            Ac[R - 4 + k] += sum;
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < R; ++m) acc[m] = v * Ac[NEG ? R - 1 - m : m];
+}
+
 // Value of plane i at (gx, gy) with the forward ghost rules (domain or the
 // three-cell ghost layer of one side; anything else reads as 0).
 __device__ __forceinline__ double f_at(const AdjArgs& a, int i, int gx, int gy)
@@ -249,7 +353,8 @@ __device__ __forceinline__ double wall_term(const AdjArgs& a, int j, int wx, int
 template <int R, int G, bool BND>
 __device__ __forceinline__ void adj_planes(const AdjArgs& a, int grp, int x0, int y0, int lane,
                                            const TileMapG& tf, const TileMapG& tl, double* s_f,
-                                           double* s_l, double* s_ax, const double (&K0)[R],
+                                           double* s_l, double* s_ax, double* s_xl,
+                                           const double (&K0)[R],
                                            const double (&Kx)[R], const double (&Ky)[R],
                                            const double (&KE)[R])
 {
@@ -276,15 +381,23 @@ __device__ __forceinline__ void adj_planes(const AdjArgs& a, int grp, int x0, in
         const double vx = a.k.vx[i], vy = a.k.vy[i];
         {  // x strips: lane -> (row r = lane % R, strip s = lane / R)
             const int r = lane % R, s = lane / R;
-            double fw[R + 8], lw[R + 6], acc[R];
+            double acc[R];
+            if constexpr (R >= 4) {
+                if (vx < 0.0)
+                    gather_x_row<R, true>(s_f, s_l, s_xl, s_xl + 256, lane, vx, a.cx, eps, acc);
+                else
+                    gather_x_row<R, false>(s_f, s_l, s_xl, s_xl + 256, lane, vx, a.cx, eps, acc);
+            } else {
+                double fw[R + 8], lw[R + 6];
 #pragma unroll
-            for (int q = 0; q < R + 8; ++q) fw[q] = s_f[(r + FH) * AP + s * R + q];
+                for (int q = 0; q < R + 8; ++q) fw[q] = s_f[(r + FH) * AP + s * R + q];
 #pragma unroll
-            for (int q = 0; q < R + 6; ++q) lw[q] = s_l[(r + LH) * AP + s * R + q];
-            if (vx < 0.0)
-                gather_strip<R, true>(fw, lw, vx, a.cx, eps, acc);
-            else
-                gather_strip<R, false>(fw, lw, vx, a.cx, eps, acc);
+                for (int q = 0; q < R + 6; ++q) lw[q] = s_l[(r + LH) * AP + s * R + q];
+                if (vx < 0.0)
+                    gather_strip<R, true>(fw, lw, vx, a.cx, eps, acc);
+                else
+                    gather_strip<R, false>(fw, lw, vx, a.cx, eps, acc);
+            }
 #pragma unroll
             for (int m = 0; m < R; ++m) s_ax[r * AXP + s * R + m] = acc[m];
         }
@@ -414,6 +527,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_
     __shared__ double s_f[SF::SLOTS];
     __shared__ double s_l[SL::SLOTS];
     __shared__ double s_ax[R * AXP];
+    __shared__ double s_xl[R >= 4 ? 256 + 16 * R : 1];  // x faces shared along a row
 
     const int b = blockIdx.x;
     const int work = (b & 7) * a.per_xcd + (b >> 3);
@@ -455,9 +569,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_
     const TileMapG tf = tile_map_g<R, FH, false>(g, x0, y0, lane, !interior);
     const TileMapG tl = tile_map_g<R, LH, true>(g, x0, y0, lane, !interior);
     if (interior)
-        adj_planes<R, G, false>(a, grp, x0, y0, lane, tf, tl, s_f, s_l, s_ax, K0, Kx, Ky, KE);
+        adj_planes<R, G, false>(a, grp, x0, y0, lane, tf, tl, s_f, s_l, s_ax, s_xl, K0, Kx, Ky,
+                                KE);
     else
-        adj_planes<R, G, true>(a, grp, x0, y0, lane, tf, tl, s_f, s_l, s_ax, K0, Kx, Ky, KE);
+        adj_planes<R, G, true>(a, grp, x0, y0, lane, tf, tl, s_f, s_l, s_ax, s_xl, K0, Kx, Ky,
+                               KE);
 }
 
 // State pass of the reverse step, one thread per cell: the K's of phase 1
