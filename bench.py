@@ -25,6 +25,11 @@ Other modes (for the rocprofv3 runs whose summaries live in profiles/):
   --pmc-run        a few steps of the main workload plus a 512 MiB device
                    copy, for one counter pass
   --summarize ...  turn the kernel-trace and counter CSVs into the summary
+  --only PART      run one of the other workloads alone (forward2048, batch,
+                   adjoint) and print its figures as one JSON line
+  --trace-table D  per-kernel, per-grid-size durations of a rocprofv3
+                   kernel trace under D, as a markdown table
+  --counter-table D  the same for the counter values of one counter pass
 """
 from __future__ import annotations
 
@@ -289,11 +294,76 @@ def cpu_baseline(setup, seconds):
                       f"of its steps from the same initial state, {dt:.1f} s on {threads} threads"}
 
 
+def trace_table(root, match):
+    """Markdown table of a rocprofv3 kernel trace: dispatches grouped by
+    kernel and grid size, with their count and mean and median durations."""
+    rows = _rows(os.path.join(root, "**", "*kernel_trace.csv"))
+    if not rows:
+        raise SystemExit(f"no kernel trace under {root}")
+    by = {}
+    for r in rows:
+        name = re.sub(r"^void ", "", r["Kernel_Name"]).split("(")[0]
+        if match and not any(m in name for m in match):
+            continue
+        ns = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        by.setdefault((name, int(r["Grid_Size_X"])), []).append(ns)
+    lines = ["| kernel | grid (work-items) | dispatches | mean us | median us |",
+             "|---|---|---|---|---|"]
+    for (name, grid), v in sorted(by.items(), key=lambda q: (q[0][0], q[0][1])):
+        lines.append(f"| `{name}` | {grid} | {len(v)} | {statistics.mean(v) / 1e3:.2f} | "
+                     f"{statistics.median(v) / 1e3:.2f} |")
+    print("\n".join(lines))
+
+
+def counter_table(root, match):
+    """Markdown table of one rocprofv3 counter pass: the mean value per
+    dispatch of each counter, grouped by kernel and grid size (FETCH_SIZE
+    and WRITE_SIZE in KiB)."""
+    rows = _rows(os.path.join(root, "**", "*counter_collection.csv"))
+    if not rows:
+        raise SystemExit(f"no counter collection under {root}")
+    by = {}
+    for r in rows:
+        name = re.sub(r"^void ", "", r["Kernel_Name"]).split("(")[0]
+        if match and not any(m in name for m in match):
+            continue
+        key = (name, int(r["Grid_Size"]), r["Counter_Name"])
+        by.setdefault(key, []).append(float(r["Counter_Value"]))
+    lines = ["| kernel | grid (work-items) | counter | dispatches | mean per dispatch |",
+             "|---|---|---|---|---|"]
+    for (name, grid, ctr), v in sorted(by.items()):
+        lines.append(f"| `{name}` | {grid} | {ctr} | {len(v)} | {statistics.mean(v):.1f} |")
+    print("\n".join(lines))
+
+
 # ---------------------------------------------------------------------------
 def pmc_run(args):
-    """A short run for one rocprofv3 counter pass: the tuned main step and a
+    """A short run for one rocprofv3 counter pass: the tuned main step (with
+    --only adjoint: ten 2048^2 reverse steps of variant --variant) and a
     plain device copy of COPY_BYTES."""
     import torch
+    from paper_1010_4124_amd import inputs, lbm, tune
+    if args.only == "adjoint":
+        s = inputs.khi(2048, 2048, Dv=0.01, Drho=0.04)
+        ctx = lbm.Context.from_setup(s)
+        f0 = ctx.init(*s.fields())
+        ctx.adj_variant = 0 if args.variant is None else args.variant
+        log(f"pmc run: reverse step variant {ctx.adj_variant} "
+            f"{lbm.lbm_adjoint_variant_info(ctx.adj_variant)}")
+        lam = [torch.randn_like(f0), ctx.empty_f()]
+        for q in range(10):
+            ctx.adjoint_step(f0, lam[q % 2], 1e-5, out=lam[(q + 1) % 2])
+        del ctx, f0, lam
+        torch.cuda.empty_cache()
+    else:
+        _pmc_main(args)
+    x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+
+
+def _pmc_main(args):
     from paper_1010_4124_amd import lbm, tune
     s = main_setup()
     ctx = lbm.Context.from_setup(s)
@@ -304,10 +374,6 @@ def pmc_run(args):
         ctx.variant = args.variant
     log(f"pmc run: variant {ctx.variant} {lbm.lbm_step_variant_info(ctx.variant)}")
     ctx.step(f0, args.steps, out=ctx.empty_f())
-    x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
-    y = torch.empty_like(x)
-    y.copy_(x)
-    torch.cuda.synchronize()
 
 
 def _rows(pattern):
@@ -407,6 +473,10 @@ def main():
     ap.add_argument("--pmc-run", action="store_true")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE", "FETCH", "WRITE"))
     ap.add_argument("--commands", nargs="*")
+    ap.add_argument("--only", choices=("forward2048", "batch", "adjoint"))
+    ap.add_argument("--trace-table", metavar="TRACE")
+    ap.add_argument("--counter-table", metavar="PMC")
+    ap.add_argument("--match", nargs="*", default=[])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: one GPU only; --gpus {args.gpus} is not supported. The step shards by "
@@ -416,11 +486,22 @@ def main():
     if args.summarize:
         summarize(args)
         return
+    if args.trace_table:
+        trace_table(args.trace_table, args.match)
+        return
+    if args.counter_table:
+        counter_table(args.counter_table, args.match)
+        return
 
     import torch
     torch.cuda.set_device(0)
     if args.pmc_run:
         pmc_run(args)
+        return
+    if args.only:
+        part = {"forward2048": bench_forward_large, "batch": bench_batch,
+                "adjoint": bench_adjoint}[args.only]
+        print(json.dumps({args.only: part(args)}), flush=True)
         return
 
     s, ctx, f0, secs, wall, avg = bench_forward_main(args)

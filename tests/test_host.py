@@ -137,3 +137,19 @@ def test_stabilize_stops_at_a_bound():
     hist = stabilize.stabilize(Edge(), 0.02, 0.01, np.zeros(4), iters=10)
     assert hist[-1]["Dv"] == pytest.approx(0.08)
     assert all(b["J"] <= a["J"] for a, b in zip(hist, hist[1:]))
+
+
+def test_trace_table_groups_by_kernel_and_grid(tmp_path, capsys):
+    cols = ("Kind,Kernel_Name,Start_Timestamp,End_Timestamp,Grid_Size_X\n")
+    rows = ["KERNEL_DISPATCH,\"void lbmd::k_adjoint<4, 18, 1, true>(lbmd::AdjArgs)\",100,1100,2048",
+            "KERNEL_DISPATCH,\"void lbmd::k_adjoint<4, 18, 1, true>(lbmd::AdjArgs)\",200,3200,2048",
+            "KERNEL_DISPATCH,\"lbmd::k_adjoint<4, 18, 1, true>(lbmd::AdjArgs)\",0,8000,65536",
+            "KERNEL_DISPATCH,\"lbmd::k_init(double const*)\",0,500,256"]
+    d = tmp_path / "tr"
+    d.mkdir()
+    (d / "x_kernel_trace.csv").write_text(cols + "\n".join(rows) + "\n")
+    bench.trace_table(str(d), ["k_adjoint"])
+    out = capsys.readouterr().out.splitlines()
+    assert len(out) == 4 and "k_init" not in "".join(out)
+    assert out[2] == "| `lbmd::k_adjoint<4, 18, 1, true>` | 2048 | 2 | 2.00 | 2.00 |"
+    assert out[3] == "| `lbmd::k_adjoint<4, 18, 1, true>` | 65536 | 1 | 8.00 | 8.00 |"
