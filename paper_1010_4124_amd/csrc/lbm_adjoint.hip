@@ -46,7 +46,7 @@ struct AdjArgs {
     const double* __restrict__ kst;  // K0, Kx, Ky, KE planes (state-pass variants)
     int nx, ny;
     int bc[4];
-    int tiles_x, nwork, per_xcd;
+    int tiles_x, tiles_y, nwork, per_xcd;
     double cx, cy, ct, wdxdy;  // w dx dy: weight of the objective term
     Consts k;
 };
@@ -534,7 +534,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_
     if (work >= a.nwork) return;
     const int tile = work / G, grp = work - tile * G;
     const int lane = threadIdx.x;
-    const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
+    const int rm = strip_walk(tile, a.tiles_x, a.tiles_y);
+    const int ty = rm / a.tiles_x, tx = rm - ty * a.tiles_x;
     const int x0 = tx * ATX, y0 = ty * R;
     const int64_t plane = (int64_t)a.nx * a.ny;
     const int gx = x0 + lane;
@@ -712,7 +713,8 @@ hipError_t launch_adjoint(int variant, const double* f, const double* lam1, doub
     a.ny = ny;
     for (int s = 0; s < 4; ++s) a.bc[s] = bc[s];
     a.tiles_x = (nx + ATX - 1) / ATX;
-    a.nwork = a.tiles_x * ((ny + V.R - 1) / V.R) * V.G;
+    a.tiles_y = (ny + V.R - 1) / V.R;
+    a.nwork = a.tiles_x * a.tiles_y * V.G;
     a.per_xcd = (a.nwork + 7) / 8;
     a.cx = cx;
     a.cy = cy;

@@ -4,8 +4,9 @@
 // step of the D2V19 FDLB model (Eq. (47) of arXiv:1010.4124); the tile body
 // is in lbm_step.h. Tiles map to workgroups (G wavefronts each) XCD-major:
 // hardware dispatches consecutive workgroups round-robin over the 8 XCDs, so
-// workgroup b takes tile (b % 8) * per_xcd + b / 8 and every XCD sweeps one
-// contiguous band of tiles whose halos then meet in that XCD's L2. The
+// workgroup b takes work item (b % 8) * per_xcd + b / 8 and every XCD sweeps
+// one contiguous stretch of the strip walk (strip_walk), whose tiles' halos
+// then meet in that XCD's L2. The
 // per-context constants travel by value in the kernel arguments and are read
 // with scalar loads.
 //
@@ -23,7 +24,8 @@ struct StepArgs {
     double* __restrict__ ke_part;  // [ntiles][2] or null
     const double* __restrict__ m_in;  // carried moment sums [4][ny][nx] (M variants)
     double* __restrict__ m_out;
-    int nwork, per_xcd;  // work items: tiles (M = 1) or tiles x groups (M = 0)
+    int tiles_y;
+    int nwork, per_xcd;  // work items: tiles (M = 1) or tiles x groups (M = 0, 2)
     Consts k;
 };
 
@@ -37,7 +39,8 @@ void k_step(StepArgs a)
     const int work = (b & 7) * a.per_xcd + (b >> 3);
     if (work >= a.nwork) return;
     constexpr int GW = MODE == PH_CARRY ? 1 : G;  // groups per work item's tile index
-    const int tile = work / GW, grp = work - tile * GW;
+    const int pos = work / GW, grp = work - pos * GW;
+    const int tile = strip_walk(pos, a.s.tiles_x, a.tiles_y);
     step_work<R, G, DEPTH, NT, MODE>(a.s, a.k, SideEqConsts{}, tile, grp,
                                    a.ke_part ? a.ke_part + 2 * tile : nullptr, lds, a.m_in,
                                    a.m_out);
@@ -332,7 +335,8 @@ hipError_t launch_step(int variant, const double* fin, double* fout, const Const
     a.ke_part = ke_part;
     a.m_in = m_in;
     a.m_out = m_out;
-    a.nwork = a.s.tiles_x * ((ny + V.R - 1) / V.R) * (V.M == PH_CARRY ? 1 : V.G);
+    a.tiles_y = (ny + V.R - 1) / V.R;
+    a.nwork = a.s.tiles_x * a.tiles_y * (V.M == PH_CARRY ? 1 : V.G);
     a.per_xcd = (a.nwork + 7) / 8;
     a.k = k;
     hipLaunchKernelGGL(V.kernel, dim3(8 * a.per_xcd), dim3(64 * (V.M == PH_CARRY ? V.G : 1)), 0,

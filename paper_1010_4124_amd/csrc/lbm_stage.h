@@ -94,6 +94,25 @@ __device__ __forceinline__ void x_source_g(const GridBC& g, int gx, int& col, in
     }
 }
 
+// Tile walk of the tile-parallel kernels: the tiles_x x tiles_y tile grid is
+// cut into strips of STRIP tile columns (the last one possibly narrower), each
+// walked row by row. Work items that follow each other are then vertical
+// neighbours within a strip and find the halo rows they share in L2; on a
+// wide grid a row-major walk moves on before they are reused (at 2048 cells
+// wide and 4-row tiles, one tile row of the reverse step touches ~6.5 MB,
+// more than an XCD's 4 MB L2). Grids at most STRIP tiles wide are walked row
+// by row. Returns the tile's row-major index ty * tiles_x + tx.
+constexpr int STRIP = 8;
+
+__device__ __forceinline__ int strip_walk(int t, int tiles_x, int tiles_y)
+{
+    const int s = t / (STRIP * tiles_y);
+    const int w = min(STRIP, tiles_x - s * STRIP);
+    const int i = t - s * STRIP * tiles_y;
+    const int ty = i / w;
+    return ty * tiles_x + s * STRIP + (i - ty * w);
+}
+
 // v mapped once around a periodic axis of n >= the halo depth: the column
 // of every halo value a fast tile (fast_tile) stages.
 __device__ __forceinline__ int wrap_once(int v, int n)

@@ -29,7 +29,9 @@ SIDES = [(1.1, 0.05, 0.0, 0.9), (0.8, -0.05, 0.02, 1.05), (1.0, 0.0, 0.05, 1.0),
          (0.9, 0.1, -0.05, 0.85)]
 CASES = [((67, 45), (P, P, P, P)), ((67, 45), (P, P, R, R)), ((130, 37), (R, R, F, F)),
          ((70, 41), (F, F, P, P)), ((69, 43), (R, R, R, R)), ((9, 7), (R, R, R, R)),
-         ((5, 6), (P, P, R, R)), ((3, 4), (R, R, P, P)), ((2, 3), (P, P, P, P))]
+         ((5, 6), (P, P, R, R)), ((3, 4), (R, R, P, P)), ((2, 3), (P, P, P, P)),
+         # wider than one strip of the tile walk (8 tiles)
+         ((600, 21), (P, P, R, R)), ((1090, 9), (R, R, P, P))]
 
 
 def _state(nx, ny, seed):

@@ -59,6 +59,11 @@ CASES = {
                                              Dv=0.01, Drho=0.01, pert=1e-2),
     "fixed-x-walls-y-64x22": lambda: generic(64, 22, (F, F, R, R), 19),
     "outflow-x-128x41": lambda: generic(128, 41, (O, O, P, P), 20),
+    # wider than one strip of the tile walk (8 tiles): a full strip and a
+    # narrower last one
+    "strips-khi-600x29": lambda: inputs.khi(600, 29, dx=1e-3, dy=1e-3, dt=1e-5, tau=1e-5,
+                                            Dv=0.01, Drho=0.01, pert=1e-2),
+    "strips-outflow-x-1100x13": lambda: generic(1100, 13, (O, O, P, P), 23),
 }
 
 
