@@ -447,21 +447,22 @@ __device__ __forceinline__ void adj_planes(const AdjArgs& a, int grp, int x0, in
     }
 }
 
-// Per-cell terms of phase 1 for the cell whose plane-0 values sit at pf
-// (f^n) and pl (lambda^{n+1}), planes `plane` apart: the sums over i of
-// lambda'_i times the partials of f_i^eq through (rho, j, E), scaled by
-// dt/tau, plus the objective's gradient w dx dy (u_y v_iy - u_y^2/2).
+// Per-cell terms of phase 1 for one cell, given its f^n (fv(i)) and
+// lambda^{n+1} (lv(i)) values, i = 0..18: the sums over i of lambda'_i times
+// the partials of f_i^eq through (rho, j, E), scaled by dt/tau, plus the
+// objective's gradient w dx dy (u_y v_iy - u_y^2/2).
 struct AdjCell {
     double K0, Kx, Ky, KE, rest;  // rest: the rest particle's adjoint
 };
 
-__device__ __forceinline__ AdjCell adj_cell(const double* pf, const double* pl, int64_t plane,
-                                            const Consts& k, double ct, double wdxdy)
+template <class FV, class LV>
+__device__ __forceinline__ AdjCell adj_cell(FV&& fv, LV&& lv, const Consts& k, double ct,
+                                            double wdxdy)
 {
     double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-        const double fi = pf[i * plane];
+        const double fi = fv(i);
         r += fi;
         jx = __builtin_fma(fi, k.vx[i], jx);
         jy = __builtin_fma(fi, k.vy[i], jy);
@@ -482,7 +483,7 @@ __device__ __forceinline__ AdjCell adj_cell(const double* pf, const double* pl, 
     double sP = 0.0, sX = 0.0, sY = 0.0, sT = 0.0, l0 = 0.0;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-        const double L = pl[i * plane];
+        const double L = lv(i);
         if (i == 0) l0 = L;
         // weight of the speed shell of velocity i and its T derivative
         const double Fs = i == 0 ? F0 : i < 7 ? F1 : i < 13 ? F2 : F3;
@@ -556,7 +557,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_
             Ky[m] = a.kst[2 * plane + c];
             KE[m] = a.kst[3 * plane + c];
         } else {
-            const AdjCell q = adj_cell(a.f + c, a.lam1 + c, plane, a.k, a.ct, a.wdxdy);
+            // loads at their point of use: these variants have no registers
+            // to spare for 38 values in flight
+            const double* pf = a.f + c;
+            const double* pl = a.lam1 + c;
+            const AdjCell q = adj_cell([&](int i) { return pf[i * plane]; },
+                                       [&](int i) { return pl[i * plane]; }, a.k, a.ct, a.wdxdy);
             K0[m] = q.K0;
             Kx[m] = q.Kx;
             Ky[m] = q.Ky;
@@ -587,7 +593,17 @@ __global__ __launch_bounds__(256) void k_adj_state(const double* __restrict__ f,
 {
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (c >= n) return;
-    const AdjCell q = adj_cell(f + c, lam1 + c, n, k, ct, wdxdy);
+    // all 38 values are loaded before any is used, so that their latencies
+    // overlap (left to itself the scheduler issues each load just before its
+    // first use and waits for it: 38 round trips in sequence)
+    double fv[NV], lv[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) fv[i] = f[i * n + c];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) lv[i] = lam1[i * n + c];
+    __builtin_amdgcn_sched_barrier(0);
+    const AdjCell q = adj_cell([&](int i) { return fv[i]; }, [&](int i) { return lv[i]; }, k, ct,
+                               wdxdy);
     kst[c] = q.K0;
     kst[n + c] = q.Kx;
     kst[2 * n + c] = q.Ky;
