@@ -59,6 +59,28 @@ def test_adjoint_step_parity(shape, bc):
         assert torch.equal(got, again)
 
 
+def test_full_size_reverse_step():
+    """The reverse step at the sizes the bench times it (256^2 and 2048^2
+    shear layers, walls in y), every variant (the bench runs the one its
+    tuner picks): the whole grid against the oracle."""
+    for n, Dv, Drho in ((256, 0.02, 0.02), (2048, 0.01, 0.04)):
+        s = inputs.khi(n, n, Dv=Dv, Drho=Drho)
+        p = oracle.OracleParams.make(s.nx, s.ny, s.dx, s.dy, s.dt, s.tau, s.bc)
+        f = oracle.init(p, *s.fields())
+        lam = inputs.random_like(f.shape, 7)
+        ref = oracle.adjoint_step(p, f, lam, 0.5)
+        ctx = lbm.Context.from_setup(s)
+        fg, lg = torch.from_numpy(f).cuda(), torch.from_numpy(lam).cuda()
+        for v in range(lbm.lbm_adjoint_variant_count()):
+            ctx.adj_variant = v
+            err = nrel(ctx.adjoint_step(fg, lg, 0.5).cpu().numpy(), ref)
+            print(f"reverse step {n}^2 variant {lbm.lbm_adjoint_variant_info(v)}: {err:.2e}",
+                  flush=True)
+            assert err < TOL, (n, v, err)
+        del fg, lg, ctx
+        torch.cuda.empty_cache()
+
+
 def test_adjoint_objective_term_only():
     nx, ny = 40, 33
     p = oracle.OracleParams.make(nx, ny, 1e-2, 1e-2, 1e-4, 1e-4, (P, P, R, R))
