@@ -59,11 +59,19 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# what the profiled step kernels (k_step, k_state) are compiled from: their
+# translation unit, the headers it includes and the build script's flags
+STEP_SOURCES = [os.path.join(ROOT, "paper_1010_4124_amd", "csrc", f) for f in
+                ("lbm_forward.hip", "lbm_device.h", "lbm_internal.h", "lbm_stage.h",
+                 "lbm_step.h")] + [os.path.join(ROOT, "include", "lbm.h"),
+                                   os.path.join(ROOT, "paper_1010_4124_amd", "build.py")]
+
+
 def source_hash():
-    """Hash of the kernel sources: counter summaries apply only to these."""
+    """Hash of STEP_SOURCES: a counter summary applies only to kernels built
+    from the sources it was taken on."""
     h = hashlib.sha1()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1010_4124_amd", "csrc", "*")) +
-                   [os.path.join(ROOT, "paper_1010_4124_amd", "build.py")])
+    files = sorted(STEP_SOURCES)
     for p in files:
         h.update(os.path.basename(p).encode())
         with open(p, "rb") as fh:
@@ -237,8 +245,12 @@ def bench_batch(args):
     b = lbm.Batch.from_setups(setups)
     fields = [s.fields() for s in setups]
     f0 = b.init(*[b.pack_scalars([f[q] for f in fields]) for q in range(4)])
-    tune.tune_batch(b, f0, slots=(0, 384), use_cache=False)
-    b.schedule = (b.schedule[0], 100)
+    if args.batch_variant is None:
+        tune.tune_batch(b, f0, slots=(0, 384), use_cache=False)
+        b.schedule = (b.schedule[0], 100)
+    else:
+        b.variant = args.batch_variant
+        b.schedule = (0, 100)
     out = b.empty_f()
     ke = torch.empty((b.n, args.batch_steps, 2), dtype=torch.float64, device=out.device)
     lbm.lbm_batch_step(b.handle, f0, out, 100, ke[:, :100].contiguous())  # warm: capture graph
@@ -470,6 +482,8 @@ def main():
     ap.add_argument("--adj-steps", type=int, default=4000)
     ap.add_argument("--adj-large-steps", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=10000)
+    ap.add_argument("--batch-variant", type=int, default=None,
+                    help="step variant of the batched sweep (default: autotuned)")
     ap.add_argument("--pmc-run", action="store_true")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE", "FETCH", "WRITE"))
     ap.add_argument("--commands", nargs="*")

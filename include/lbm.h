@@ -206,9 +206,11 @@ int lbm_set_step_variant(lbm_ctx* ctx, int32_t variant);
 int lbm_get_step_variant(lbm_ctx* ctx, int32_t* variant);
 
 /* Autotuner. Times the step variants variants[0..nv) (nv = 0: all of them)
- * on this context's grid: 2 warm-up steps, then nsteps >= 1 timed steps of
- * lbm_step from f_in into f_tmp (f_in is not modified), bracketed by HIP
- * events on `stream`. ms_out: NULL or host double[nv or count] receiving
+ * on this context's grid: 2 warm-up steps, then one call of nsteps >= 1 and
+ * one of 2 nsteps steps of lbm_step from f_in into f_tmp (f_in is not
+ * modified), each bracketed by HIP events on `stream`; the time per step is
+ * the difference of the two over nsteps, so that a call's fixed cost does
+ * not count. ms_out: NULL or host double[nv or count] receiving
  * milliseconds per step. Leaves the fastest variant selected. Synchronous
  * (waits for the timed work); on error the previous variant is kept.
  * LBM_EUNSUPPORTED when the context's scheme is not WENO5 (the variants are

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -692,20 +693,28 @@ static int batch_tune_impl(lbm_batch* b, const double* f_in, double* f_tmp, int3
     int best_v = keep_v, best_s = keep_s, rc = LBM_OK;
     double best_ms = 0.0;
     b->graph_chunk = 0;
+    // milliseconds of one call of n steps
+    auto timed = [&](int32_t n, float& ms) -> int {
+        if ((e = hipEventRecord(e0, st)) != hipSuccess) return bhip(e, "tune");
+        const int r = lbm_batch_step(b, f_in, f_tmp, n, nullptr, stream);
+        if (r != LBM_OK) return r;
+        if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+            (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess)
+            return bhip(e, "tune");
+        return LBM_OK;
+    };
+    const int32_t n2 = nsteps <= INT32_MAX / 2 ? 2 * nsteps : nsteps;
     for (int j = 0; j < cv && rc == LBM_OK; ++j) {
         if ((rc = lbm_batch_set_step_variant(b, nv > 0 ? variants[j] : j)) != LBM_OK) break;
         for (int q = 0; q < cs && rc == LBM_OK; ++q) {
             b->slots = ns > 0 ? slots[q] : keep_s;
-            float ms = 0.f;
+            float t1 = 0.f, t2 = 0.f;
             if ((rc = lbm_batch_step(b, f_in, f_tmp, 2, nullptr, stream)) != LBM_OK) break;
-            if ((e = hipEventRecord(e0, st)) != hipSuccess) { rc = bhip(e, "tune"); break; }
-            if ((rc = lbm_batch_step(b, f_in, f_tmp, nsteps, nullptr, stream)) != LBM_OK) break;
-            if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
-                (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
-                rc = bhip(e, "tune");
-                break;
-            }
-            const double per = ms / nsteps;
+            if ((rc = timed(nsteps, t1)) != LBM_OK || (rc = timed(n2, t2)) != LBM_OK) break;
+            // per step from the difference of the two calls: a call's fixed
+            // cost (the carried-moment mode's sums pass over f_in) cancels
+            const double per = n2 > nsteps && t2 > t1 ? (double)(t2 - t1) / (n2 - nsteps)
+                                                      : (double)t2 / n2;
             if (ms_out) ms_out[j * cs + q] = per;
             if ((j == 0 && q == 0) || per < best_ms) {
                 best_ms = per;

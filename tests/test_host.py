@@ -44,8 +44,24 @@ def test_traffic_needs_matching_sources_and_kernel(tmp_path):
 
 
 def test_source_hash_covers_the_kernel_sources():
+    import os
     h = bench.source_hash()
     assert isinstance(h, str) and len(h) >= 16 and h == bench.source_hash()
+    # every file the step kernels' translation unit includes is covered
+    csrc = os.path.join(bench.ROOT, "paper_1010_4124_amd", "csrc")
+    names = {os.path.basename(p) for p in bench.STEP_SOURCES}
+    with open(os.path.join(csrc, "lbm_forward.hip")) as fh:
+        todo = [ln.split('"')[1] for ln in fh if ln.startswith('#include "')]
+    seen = set()
+    while todo:
+        f = todo.pop()
+        if f in seen:
+            continue
+        seen.add(f)
+        assert f in names, f
+        p = os.path.join(csrc, f) if f != "lbm.h" else os.path.join(bench.ROOT, "include", f)
+        with open(p) as fh:
+            todo += [ln.split('"')[1] for ln in fh if ln.startswith('#include "')]
 
 
 # --- inputs --------------------------------------------------------------------
