@@ -46,8 +46,13 @@ class Schedule:
         K1 = K2 * max(1, K1 // K2)
         return cls(K1, K2)
 
-    def peak_states(self, nsteps):
-        return math.ceil(nsteps / self.K1) + math.ceil(self.K1 / self.K2) + self.K2 + 2
+    def peak_states(self, nsteps, overlap=False):
+        """Live 19-plane states of a gradient: level-1 and level-2
+        checkpoints, one piece's states, lambda and its partner; the
+        overlapped gradient adds one more piece and one more set of level-2
+        checkpoints."""
+        seq = math.ceil(nsteps / self.K1) + math.ceil(self.K1 / self.K2) + self.K2 + 2
+        return seq + (math.ceil(self.K1 / self.K2) + self.K2 if overlap else 0)
 
 
 class KHIProblem:
@@ -62,8 +67,9 @@ class KHIProblem:
             raise ValueError("window must satisfy 0 <= n0 <= n1 <= nsteps")
         self.phys = dict(rho1=rho1, rho2=rho2, u0=u0, p0=p0, yw=yw)
         self.schedule = schedule or Schedule.every(min(200, max(1, self.nsteps)))
-        bc = (inputs.PERIODIC, inputs.PERIODIC, inputs.REFLECT, inputs.REFLECT)
-        self.ctx = lbm.Context(nx, ny, dx, dy, dt, tau, bc)
+        self.bc = (inputs.PERIODIC, inputs.PERIODIC, inputs.REFLECT, inputs.REFLECT)
+        self.ctx = lbm.Context(nx, ny, dx, dy, dt, tau, self.bc)
+        self._ctx2 = None  # the recompute context of the overlapped gradient
         if variant is not None:
             self.ctx.variant = variant
 
@@ -99,38 +105,96 @@ class KHIProblem:
         return J, ck
 
     # -- backward --------------------------------------------------------------
-    def gradient(self, Dv, Drho, amps, ck=None, scale=1.0):
-        """(dJ/dD_v, dJ/dD_rho, dJ/da) by the discrete adjoint."""
+    def _units(self, ck):
+        """The reverse sweep's work units in the order it takes them:
+        (c0, c1, s0, s1) = level-1 segment [c0, c1) and its level-2 piece
+        [s0, s1), last first."""
+        N, K1, K2 = self.nsteps, self.schedule.K1, self.schedule.K2
+        out = []
+        for c0 in sorted(ck, reverse=True):
+            c1 = min(c0 + K1, N)
+            for s0 in reversed(range(c0, c1, K2)):
+                out.append((c0, c1, s0, min(s0 + K2, c1)))
+        return out
+
+    def _recompute(self, ctx, ck, units):
+        """States f^s0 .. f^(s1-1) of each unit in turn, recomputed from the
+        level-1 checkpoints (and, per level-1 segment, its level-2
+        checkpoints every K2 steps) on ctx."""
+        K2 = self.schedule.K2
+        seg, sub = None, {}
+        for c0, c1, s0, s1 in units:
+            if c0 != seg:
+                seg, f, sub = c0, ck[c0], {c0: ck[c0]}
+                for n in range(c0 + K2, c1, K2):
+                    f = ctx.step(f, K2)
+                    sub[n] = f
+            states = [sub.pop(s0)]
+            for _ in range(s0 + 1, s1):
+                states.append(ctx.step(states[-1], 1))
+            yield states
+
+    def gradient(self, Dv, Drho, amps, ck=None, scale=1.0, overlap=True):
+        """(dJ/dD_v, dJ/dD_rho, dJ/da) by the discrete adjoint.
+
+        overlap: recompute the next unit's states on a second context and
+        stream while the current unit's reverse steps run (the two are
+        independent), so that grids too small to fill the GPU alone share it;
+        at most one more unit's states and one more segment's level-2
+        checkpoints are alive. The result is the same bit for bit."""
         if ck is None:
             _, ck = self.run(Dv, Drho, amps)
         ctx = self.ctx
-        N, K1, K2 = self.nsteps, self.schedule.K1, self.schedule.K2
+        N = self.nsteps
         zero = torch.zeros((19, self.ny, self.nx), dtype=torch.float64, device=ctx.device)
         # lambda^N = w_N dE_y/df^N: the adjoint step with a zero seed
         fN = self._advance(ck[max(ck)], max(ck), N)
         lam = ctx.adjoint_step(fN, zero, scale * self.weight(N))
         del fN
         lam_next = ctx.empty_f()
-        for c0 in sorted(ck, reverse=True):
-            c1 = min(c0 + K1, N)
-            # level 2: checkpoints every K2 inside [c0, c1)
-            sub = {c0: ck[c0]}
-            f = ck[c0]
-            for n in range(c0, c1, K2):
-                if n != c0:
-                    sub[n] = f
-                if n + K2 < c1:
-                    f = ctx.step(f, K2)
-            for s0 in sorted(sub, reverse=True):
-                s1 = min(s0 + K2, c1)
-                states = [sub[s0]]
-                for _ in range(s0 + 1, s1):
-                    states.append(ctx.step(states[-1], 1))
-                for n in range(s1 - 1, s0 - 1, -1):
-                    ctx.adjoint_step(states[n - s0], lam, scale * self.weight(n), out=lam_next)
-                    lam, lam_next = lam_next, lam
+        units = self._units(ck)
+
+        def reverse(unit, states):
+            _, _, s0, s1 = unit
+            nonlocal lam, lam_next
+            for n in range(s1 - 1, s0 - 1, -1):
+                ctx.adjoint_step(states[n - s0], lam, scale * self.weight(n), out=lam_next)
+                lam, lam_next = lam_next, lam
+
+        if not overlap:
+            for unit, states in zip(units, self._recompute(ctx, ck, units)):
+                reverse(unit, states)
                 del states
-            del sub
+        else:
+            main = torch.cuda.current_stream()
+            side = torch.cuda.Stream()  # default priority
+            if self._ctx2 is None:
+                self._ctx2 = lbm.Context(self.nx, self.ny, self.dx, self.dy, self.dt, self.tau,
+                                         self.bc)
+            self._ctx2.variant = ctx.variant
+            side.wait_stream(main)  # the checkpoints are complete
+            for f in ck.values():
+                f.record_stream(side)
+            gen = self._recompute(self._ctx2, ck, units)
+
+            def produce():
+                with torch.cuda.stream(side):
+                    states = next(gen, None)
+                    done = torch.cuda.Event()
+                    done.record(side)
+                return states, done
+
+            ahead = produce()
+            for i, unit in enumerate(units):
+                (states, done), ahead = ahead, None
+                if i + 1 < len(units):
+                    ahead = produce()  # queued on the side stream before this unit's reverse steps
+                main.wait_event(done)
+                for t in states:
+                    t.record_stream(main)
+                reverse(unit, states)
+                del states
+            main.wait_stream(side)
         s = self.fields(Dv, Drho, amps)
         g_rho, g_ux, g_uy, g_T = ctx.init_vjp(*s.fields(), lam)
         t = inputs.khi_tangents(self.nx, self.ny, self.dx, self.dy, float(Dv), float(Drho),

@@ -97,3 +97,17 @@ def test_full_size_gradient_vs_central_fd():
     assert gDv == pytest.approx(fd_dv, rel=1e-5)
     assert gDrho == pytest.approx(fd_dr, rel=1e-5)
     assert np.dot(ga, d) == pytest.approx(fd_a, rel=1e-5)
+
+
+@pytest.mark.parametrize("nsteps,sch", [(60, Schedule(30, 6)), (70, Schedule(30, 6)),
+                                        (45, Schedule(16, 5)), (40, Schedule.every(40))])
+def test_overlapped_gradient_is_the_sequential_one(nsteps, sch):
+    """Recomputing the next piece on a second stream while the current one is
+    reversed changes nothing: the gradient is the sequential one bit for bit
+    (ragged last segments and pieces included)."""
+    prob = KHIProblem(64, 40, nsteps=nsteps, window=(nsteps // 3, nsteps), schedule=sch)
+    amps = inputs.mode_amplitudes(64, seed=5, base=1e-2)
+    _, ck = prob.run(0.008, 0.01, amps)
+    a = prob.gradient(0.008, 0.01, amps, ck, overlap=False)
+    b = prob.gradient(0.008, 0.01, amps, ck, overlap=True)
+    assert a[0] == b[0] and a[1] == b[1] and np.array_equal(a[2], b[2])
