@@ -15,7 +15,9 @@ HBM traffic (19 FP64 values read + 19 written = 304 B per site update) to the
 the stream the kernel runs on bracket the timed region, which holds exactly
 `steps` launches of the step kernel and nothing else; `traffic` is the
 measured HBM traffic per launch from the committed rocprofv3 counter summary
-when it was taken on the current kernel sources. `extra` holds the other
+when it was taken on the current kernel sources. The timed run is repeated
+(--repeats, default 5 runs in all) and the spread goes to
+`extra.forward_512_repeats`; `value` is the first run. `extra` holds the other
 workloads: the 2048^2 forward step, the adjoint (reverse step alone and the
 full checkpointed gradient), the 64-instance batched sweep and the paper's
 transition-layer studies on its own shear layer. `cpu_baseline`
@@ -147,7 +149,15 @@ def bench_forward_main(args):
     avg = secs / args.steps  # the timed region holds exactly these step launches
     log(f"forward 512^2: {lups / secs / 1e6:.1f} MLUPS ({secs:.3f} s events, {wall:.3f} s wall), "
         f"{avg * 1e6:.2f} us per launch")
-    return s, ctx, f0, secs, wall, avg
+    # the same timed run repeated, for its spread (the reported value is the first)
+    runs = [secs] + [sync_time(lambda: ctx.step(f0, args.steps, out=out))[0]
+                     for _ in range(max(0, args.repeats - 1))]
+    ms = sorted(r / args.steps * 1e3 for r in runs)
+    rep = {"runs": len(runs), "ms_per_step": [r / args.steps * 1e3 for r in runs],
+           "median_ms_per_step": statistics.median(ms),
+           "median_MLUPS": s.nx * s.ny / statistics.median(ms) / 1e3}
+    log(f"forward 512^2 repeats: {rep}")
+    return s, ctx, f0, secs, wall, avg, rep
 
 
 def bench_forward_large(args):
@@ -473,6 +483,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed runs of the main workload; the first is the reported value")
     ap.add_argument("--variant", type=int, default=None,
                     help="step variant of the main workload (default: autotuned)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -518,7 +530,7 @@ def main():
         print(json.dumps({args.only: part(args)}), flush=True)
         return
 
-    s, ctx, f0, secs, wall, avg = bench_forward_main(args)
+    s, ctx, f0, secs, wall, avg, rep = bench_forward_main(args)
     lups = s.nx * s.ny * args.steps
     mlups = lups / secs / 1e6
     kname = step_kernel_name(ctx.variant)
@@ -528,7 +540,7 @@ def main():
     del ctx, f0
     torch.cuda.empty_cache()
 
-    extra = {}
+    extra = {"forward_512_repeats": rep}
     if not args.no_extra:
         extra["forward_2048"] = bench_forward_large(args)
         extra["batched_sweep"] = bench_batch(args)
