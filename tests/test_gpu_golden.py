@@ -87,7 +87,7 @@ def test_khi512_full_run_matches_oracle(gold):
     ke = np.concatenate(ke)  # ke[n] = state at step n, n < 20000
     ref = gold["ke"]  # every 100 steps, 0..20000
     got = np.concatenate([ke[::every], ctx.kinetic_y(f).cpu().numpy()[None]])
-    # E_y is a small difference-dominated quantity (u_y ~ 1e-3): judge its
+    # E_y is a small difference-dominated quantity (u_y ~ 1e-3): measure its
     # error against the flow's kinetic energy sum rho |u|^2 / 2 dx dy
     r0, ux0, uy0, _ = s.fields()
     e_kin = float((0.5 * r0 * (ux0 ** 2 + uy0 ** 2)).sum()) * s.dx * s.dy
