@@ -178,6 +178,12 @@ def bench_forward_large(args):
     return r
 
 
+def _variants(ctx):
+    from paper_1010_4124_amd import lbm
+    return {"step": list(lbm.lbm_step_variant_info(ctx.variant)),
+            "reverse": list(lbm.lbm_adjoint_variant_info(ctx.adj_variant))}
+
+
 def tune_problem(prob):
     """Tune the forward and reverse step variants of a gradient problem on
     its own initial state (outside any timed region)."""
@@ -227,6 +233,7 @@ def bench_adjoint(args):
     res["gradient_256"] = {"steps": args.adj_steps, "checkpoint_every": 200,
                            "forward_MLUPS": lups / fwd_secs / 1e6,
                            "adjoint_MLUPS": lups / grad_secs / 1e6,
+                           "variants": _variants(prob.ctx),
                            "note": "adjoint = recompute + reverse, per forward step"}
     # 2048^2, sqrt-N two-level schedule over a bounded number of steps
     n2 = args.adj_large_steps
@@ -239,7 +246,8 @@ def bench_adjoint(args):
     gsecs, _ = sync_time(lambda: prob2.gradient(0.01, 0.04, amps2, ck=ck2))
     l2 = 2048 * 2048 * n2
     res["gradient_2048"] = {"steps": n2, "schedule": [prob2.schedule.K1, prob2.schedule.K2],
-                            "forward_MLUPS": l2 / fsecs / 1e6, "adjoint_MLUPS": l2 / gsecs / 1e6}
+                            "forward_MLUPS": l2 / fsecs / 1e6, "adjoint_MLUPS": l2 / gsecs / 1e6,
+                            "variants": _variants(prob2.ctx)}
     log(f"adjoint: {res}")
     del prob, prob2, ck, ck2
     torch.cuda.empty_cache()

@@ -2,6 +2,7 @@
 // parameter validation, context ownership, launch sequencing and errors.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -139,8 +140,13 @@ int lbm_create(const lbm_params* p, lbm_ctx** out)
     c->ke_cap = maxtiles > (int)((n + 255) / 256) ? maxtiles : (int)((n + 255) / 256);
     // the same buffer first receives the 4 x 19 fixed-side equilibria
     if (2 * c->ke_cap < 4 * NV) c->ke_cap = 2 * NV;
+    // energy partials of up to KE_ROWS steps, reduced by one launch (fewer
+    // rows where that would take more than 64 MiB)
+    constexpr int KE_ROWS = 32;
+    const size_t row_bytes = 2 * (size_t)c->ke_cap * sizeof(double);
+    c->ke_rows = (int)std::max<size_t>(1, std::min<size_t>(KE_ROWS, (64u << 20) / row_bytes));
     if ((e = hipMalloc(&c->scratch, NV * n * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&c->ke_part, 2 * (size_t)c->ke_cap * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&c->ke_part, row_bytes * c->ke_rows)) != hipSuccess ||
         (e = hipMalloc(&c->colbuf, (size_t)p->nx * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&c->msum, 8 * n * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&c->gbuf, NV * 2 * ((size_t)p->nx + p->ny) * sizeof(double))) !=
@@ -202,6 +208,24 @@ int lbm_init(lbm_ctx* c, const double* rho, const double* ux, const double* uy, 
     return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_init");
 }
 
+// Row of the energy partials that step s of a call writes.
+static double* ke_row(lbm_ctx* c, int s)
+{
+    return c->ke_part + 2 * (int64_t)c->ke_cap * (s % c->ke_rows);
+}
+
+// After step s of nsteps: when s fills the last row or is the last step,
+// reduce the rows written since the previous reduction into their ke_log
+// entries, one workgroup per row (each row as a single step's would be).
+static hipError_t reduce_ke_rows(lbm_ctx* c, int s, int nsteps, int nparts, double* ke_log,
+                                 hipStream_t st)
+{
+    if ((s + 1) % c->ke_rows != 0 && s != nsteps - 1) return hipSuccess;
+    const int rows = s % c->ke_rows + 1;
+    return launch_reduce_pairs(c->ke_part, nparts, rows, 2 * (int64_t)c->ke_cap,
+                               c->p.dx * c->p.dy, ke_log + 2 * (s + 1 - rows), st);
+}
+
 int lbm_step(lbm_ctx* c, const double* f_in, double* f_out, int32_t nsteps, double* ke_log,
              lbm_stream stream)
 {
@@ -226,13 +250,11 @@ int lbm_step(lbm_ctx* c, const double* f_in, double* f_out, int32_t nsteps, doub
                 e = launch_outflow(src, p.nx, p.ny, c->gb, c->k, st);
             if (e != hipSuccess) return hip_fail(e, "lbm_step outflow");
             int nparts = 0;
-            e = launch_step_lo(p.scheme, src, dst, c->k, ke_log ? c->ke_part : nullptr, &nparts,
+            e = launch_step_lo(p.scheme, src, dst, c->k, ke_log ? ke_row(c, s) : nullptr, &nparts,
                                p.nx, p.ny, p.bc, cx, cy, ct, p.ke_axis, c->gb, st);
             if (e != hipSuccess) return hip_fail(e, "lbm_step");
-            if (ke_log) {
-                e = launch_reduce_pairs(c->ke_part, nparts, p.dx * p.dy, ke_log + 2 * s, st);
-                if (e != hipSuccess) return hip_fail(e, "lbm_step ke");
-            }
+            if (ke_log && (e = reduce_ke_rows(c, s, nsteps, nparts, ke_log, st)) != hipSuccess)
+                return hip_fail(e, "lbm_step ke");
         }
         return LBM_OK;
     }
@@ -263,18 +285,16 @@ int lbm_step(lbm_ctx* c, const double* f_in, double* f_out, int32_t nsteps, doub
         } else if (mode == 2) {
             // state pass: cell state, rest particle and energy partials
             hipError_t e = launch_state(src, dst, c->msum, n, ct, p.ke_axis,
-                                        ke_log ? c->ke_part : nullptr, &nparts, c->k, st);
+                                        ke_log ? ke_row(c, s) : nullptr, &nparts, c->k, st);
             if (e != hipSuccess) return hip_fail(e, "lbm_step state");
             m_in = c->msum;
         }
         hipError_t e = launch_step(c->variant, src, dst, c->k,
-                                   ke_log && mode != 2 ? c->ke_part : nullptr, p.nx, p.ny, p.bc,
+                                   ke_log && mode != 2 ? ke_row(c, s) : nullptr, p.nx, p.ny, p.bc,
                                    cx, cy, ct, p.ke_axis, c->gb, m_in, m_out, st);
         if (e != hipSuccess) return hip_fail(e, "lbm_step");
-        if (ke_log) {
-            e = launch_reduce_pairs(c->ke_part, nparts, p.dx * p.dy, ke_log + 2 * s, st);
-            if (e != hipSuccess) return hip_fail(e, "lbm_step ke");
-        }
+        if (ke_log && (e = reduce_ke_rows(c, s, nsteps, nparts, ke_log, st)) != hipSuccess)
+            return hip_fail(e, "lbm_step ke");
     }
     return LBM_OK;
 }
@@ -299,7 +319,7 @@ int lbm_kinetic_y(lbm_ctx* c, const double* f, double* out2, lbm_stream stream)
     int np = 0;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = launch_kinetic_part(f, c->k, n, c->p.ke_axis, c->ke_part, &np, st);
-    if (e == hipSuccess) e = launch_reduce_pairs(c->ke_part, np, c->p.dx * c->p.dy, out2, st);
+    if (e == hipSuccess) e = launch_reduce_pairs(c->ke_part, np, 1, 0, c->p.dx * c->p.dy, out2, st);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_kinetic_y");
 }
 

@@ -256,12 +256,16 @@ __global__ __launch_bounds__(256) void k_kinetic_part(const double* __restrict__
     }
 }
 
-// Deterministic final reduction of n (sum, max) partials; out2[0] is scaled
-// by dxdy.
+// Deterministic final reduction of n (sum, max) partials per row, one
+// workgroup per row: row b starts at part + b * stride and its result goes to
+// out2[2b], out2[2b+1]; out2[2b] is scaled by dxdy.
 __global__ __launch_bounds__(256) void k_reduce_pairs(const double* __restrict__ part, int n,
-                                                      double dxdy, double* __restrict__ out2)
+                                                      int64_t stride, double dxdy,
+                                                      double* __restrict__ out2)
 {
     __shared__ double sr[8];
+    part += blockIdx.x * stride;
+    out2 += 2 * blockIdx.x;
     double s = 0.0, mx = 0.0;
     for (int j = threadIdx.x; j < n; j += 256) {
         s += part[2 * j];
@@ -370,10 +374,11 @@ hipError_t launch_sums(const double* f, double* m, const Consts& k, int64_t n, h
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_pairs(const double* part, int n, double dxdy, double* out2,
-                               hipStream_t st)
+hipError_t launch_reduce_pairs(const double* part, int n, int rows, int64_t stride, double dxdy,
+                               double* out2, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(256), 0, st, part, n, dxdy, out2);
+    hipLaunchKernelGGL(k_reduce_pairs, dim3((unsigned)rows), dim3(256), 0, st, part, n, stride,
+                       dxdy, out2);
     return hipGetLastError();
 }
 

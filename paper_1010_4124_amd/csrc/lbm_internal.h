@@ -13,10 +13,11 @@ struct lbm_ctx {
     int device = 0;
     int variant = 0;
     int adj_variant = 0;
-    int ke_cap = 0;
+    int ke_cap = 0;   // partials per row of ke_part
+    int ke_rows = 1;  // rows of ke_part: steps whose energy partials one launch reduces
     lbmd::Consts k;                // per-context constants (kernel arguments)
     double* scratch = nullptr;     // 19 planes: ping-pong state of multi-step calls
-    double* ke_part = nullptr;     // [ke_cap][2] diagnostic partials
+    double* ke_part = nullptr;     // [ke_rows][ke_cap][2] diagnostic partials
     double* colbuf = nullptr;      // nx doubles: column sums of lbm_sep_project
     double* msum = nullptr;        // 2 x [4][ny][nx]: carried moment sums (ping-pong)
     double* gbuf = nullptr;        // outflow ghosts: [19][ny] per x side, [19][nx] per y side
@@ -47,8 +48,8 @@ hipError_t launch_outflow(const double* f, int nx, int ny, double* const g[4], c
 hipError_t launch_sums(const double* f, double* m, const Consts& k, int64_t n, hipStream_t st);
 hipError_t launch_state(const double* f, double* fout, double* state, int64_t n, double ct,
                         int ke_axis, double* part, int* nparts, const Consts& k, hipStream_t st);
-hipError_t launch_reduce_pairs(const double* part, int n, double dxdy, double* out2,
-                               hipStream_t st);
+hipError_t launch_reduce_pairs(const double* part, int n, int rows, int64_t stride, double dxdy,
+                               double* out2, hipStream_t st);
 hipError_t launch_init(const double* rho, const double* ux, const double* uy, const double* T,
                        double* f, const Consts& k, int64_t n, hipStream_t st);
 hipError_t launch_side_eq(double* out, const double s[4][4], const Consts& k, hipStream_t st);

@@ -13,6 +13,7 @@ from __future__ import annotations
 import hashlib
 import json
 import os
+import statistics
 
 import torch
 
@@ -68,10 +69,19 @@ def _pick(ms):
     return min(k for k, v in ms.items() if v <= best * (1.0 + TIE))
 
 
+def _central(runs):
+    """Per-step time of each key from its repeated trials: the median. The
+    step and batch tuners time a step as the difference of two calls, so a
+    stall in the shorter call makes a trial read low; the median of three
+    trials discards one such outlier, where the minimum would keep it."""
+    return {k: statistics.median(v) for k, v in runs.items()}
+
+
 def tune_context(ctx, f, nsteps=None, reps=3, use_cache=True):
     """Select the fastest step variant for ctx; f is a representative state.
-    Each variant is timed `reps` times over nsteps steps (default: about
-    5e7 site updates) and keeps its best time.
+    Each variant is timed `reps` times over nsteps and 2 nsteps steps
+    (default: about 5e7 site updates) and keeps the median of its per-step
+    times.
     Returns {"variant": v, "ms": {variant: ms per step}, "cached": bool}."""
     key = context_key(ctx)
     db = _load() if use_cache else {}
@@ -82,10 +92,11 @@ def tune_context(ctx, f, nsteps=None, reps=3, use_cache=True):
     tmp = ctx.empty_f()
     if nsteps is None:
         nsteps = max(3, min(200, int(5e7 / (ctx.nx * ctx.ny))))
-    ms = {}
+    runs = {}
     for _ in range(max(1, reps)):
         for k, v in lbm.lbm_tune_step(ctx.handle, ctx.nx, ctx.ny, f, tmp, nsteps).items():
-            ms[k] = min(ms.get(k, v), v)
+            runs.setdefault(k, []).append(v)
+    ms = _central(runs)
     ctx.variant = _pick(ms)
     rec = {"variant": ctx.variant, "ms": {str(k): v for k, v in ms.items()}}
     if use_cache:
@@ -95,7 +106,7 @@ def tune_context(ctx, f, nsteps=None, reps=3, use_cache=True):
     return dict(rec, cached=False)
 
 
-def tune_batch(b, f, nsteps=None, slots=(0,), reps=2, use_cache=True):
+def tune_batch(b, f, nsteps=None, slots=(0,), reps=3, use_cache=True):
     """Select the fastest (variant, persistent slots per XCD) for batch b,
     with the same repetition and tie rule as tune_context."""
     key = batch_key(b)
@@ -108,10 +119,11 @@ def tune_batch(b, f, nsteps=None, slots=(0,), reps=2, use_cache=True):
     tmp = b.empty_f()
     if nsteps is None:
         nsteps = max(3, min(200, int(5e7 / b.cells)))
-    ms = {}
+    runs = {}
     for _ in range(max(1, reps)):
         for k, v in lbm.lbm_batch_tune(b.handle, f, tmp, nsteps, slots=slots).items():
-            ms[k] = min(ms.get(k, v), v)
+            runs.setdefault(k, []).append(v)
+    ms = _central(runs)
     v, q = _pick(ms)
     b.variant = v
     b.schedule = (q, b.schedule[1])

@@ -21,6 +21,15 @@ def test_tie_rule_picks_lowest_index_within_band():
     assert tune.TIE == pytest.approx(0.015)
 
 
+def test_median_of_trials_discards_one_low_outlier():
+    # variant 1's middle trial read low (a stall in its shorter call): the
+    # median keeps 0 the fastest where the minimum would pick 1
+    runs = {0: [1.0, 1.01, 1.02], 1: [1.3, 0.6, 1.31]}
+    ms = tune._central(runs)
+    assert ms == {0: 1.01, 1: 1.3} and tune._pick(ms) == 0
+    assert tune._pick({k: min(v) for k, v in runs.items()}) == 1
+
+
 # --- benchmark traffic figure --------------------------------------------------
 def _summary(tmp_path, name, sha, kernel, traffic):
     p = tmp_path / name
