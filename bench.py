@@ -310,18 +310,33 @@ def cpu_baseline(setup, seconds):
     import oracle
     p = oracle.OracleParams.make(setup.nx, setup.ny, setup.dx, setup.dy, setup.dt, setup.tau,
                                  setup.bc)
-    f = oracle.init(p, *setup.fields())
+    f0 = oracle.init(p, *setup.fields())
     threads = min(16, os.cpu_count() or 1)
-    steps, chunk = 0, 10
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds and steps < 5000:
-        f = oracle.step(p, f, chunk, nthreads=threads)
-        steps += chunk
-    dt = time.perf_counter() - t0
+
+    def timed(nthreads, budget):
+        f, steps, chunk = f0, 0, 10 if nthreads > 1 else 1
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget and steps < 5000:
+            f = oracle.step(p, f, chunk, nthreads=nthreads)
+            steps += chunk
+        return steps, time.perf_counter() - t0
+
+    steps, dt = timed(threads, seconds)
+    steps1, dt1 = timed(1, seconds / 3)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")),
+                         "")
+    except OSError:
+        pass
     return {"value": setup.nx * setup.ny * steps / dt / 1e6, "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
             "sample": f"{setup.nx}x{setup.ny} shear layer (the main workload), first {steps} "
-                      f"of its steps from the same initial state, {dt:.1f} s on {threads} threads"}
+                      f"of its steps from the same initial state, {dt:.1f} s on {threads} threads",
+            "single_thread_MLUPS": setup.nx * setup.ny * steps1 / dt1 / 1e6,
+            "single_thread_sample": f"first {steps1} steps, {dt1:.1f} s on 1 thread",
+            "host_cpus": os.cpu_count(), "cpu_model": model}
 
 
 def trace_table(root, match):
