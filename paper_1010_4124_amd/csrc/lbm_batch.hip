@@ -45,7 +45,7 @@ struct BatchInst {
     int ke_off;      // first per-tile (sum, max) partial of the instance
     int kp_off, kp_n;  // partials the energy reduction adds up: per tile, or per
                        // 256-cell block when a state pass forms them
-    int pad_;
+    int blk_off;       // first 256-cell block of the instance in the batch's block list
     double cx, cy, ct, dxdy;
     double side_eq[4 * NV];  // fixed-side equilibria [side][i]
 };
@@ -104,6 +104,37 @@ void k_step_batch(BatchArgs a)
 
 // Per-instance reduction of the tile partials: block i writes
 // out[i * stride + pos + {0, 1}] = (dxdy * sum, max).
+// State pass of a batch in one launch: block b is block b - blk_off of the
+// instance blk_inst[b] (state_block; its energy partial lands at global
+// block b, where the instance's kp_off points for the state-pass variants).
+__global__ __launch_bounds__(256) void k_state_batch(const double* __restrict__ fin,
+                                                     double* __restrict__ fout,
+                                                     double* __restrict__ msum,
+                                                     const int* __restrict__ blk_inst,
+                                                     const BatchInst* __restrict__ inst,
+                                                     double* __restrict__ ke_part, Consts k)
+{
+    __shared__ double sr[8];
+    const BatchInst& d = inst[blk_inst[blockIdx.x]];
+    state_block(fin + d.off, fout + d.off, msum + d.moff, (int64_t)d.nx * d.ny, d.ct, d.ke_axis,
+                ke_part ? ke_part + 2 * (int64_t)d.blk_off : nullptr, k,
+                (int64_t)blockIdx.x - d.blk_off, sr);
+}
+
+// Outflow ghosts of every outflow side of a batch in one launch: entry b of
+// oflow is (instance, side + 4 * block along the side).
+__global__ __launch_bounds__(256) void k_outflow_batch(const double* __restrict__ fin,
+                                                       const int2* __restrict__ oflow,
+                                                       const BatchInst* __restrict__ inst,
+                                                       double* gbuf, Consts k)
+{
+    const int2 e = oflow[blockIdx.x];
+    const BatchInst& d = inst[e.x];
+    const int side = e.y & 3;
+    outflow_point(fin + d.off, d.nx, d.ny, gbuf + d.goff[side], side,
+                  (e.y >> 2) * 256 + (int)threadIdx.x, k);
+}
+
 __global__ __launch_bounds__(256) void k_reduce_batch(const double* __restrict__ part,
                                                       const BatchInst* __restrict__ inst,
                                                       double* __restrict__ out, int64_t stride,
@@ -172,6 +203,9 @@ struct lbm_batch {
     double* msum = nullptr;     // 2 x (4 * cells): carried moment sums, ping-pong
     double* gbuf = nullptr;     // outflow ghost arrays of the instances that have them
     int64_t gcap = 0;
+    int* blk_inst = nullptr;    // instance of each 256-cell block (state pass)
+    int2* oflow = nullptr;      // (instance, side + 4 block) of each outflow ghost block
+    int nblk = 0, noflow = 0;
     int ring_cap = 0;
     hipStream_t cap = nullptr;  // private stream used only for capture
     struct Graph {
@@ -261,13 +295,11 @@ hipError_t launch_batch_step(lbm_batch* b, const double* src, double* dst, bool 
                              hipStream_t st)
 {
     const BatchVariant& V = kBatchVariants[b->variant];
-    // outflow ghosts of the state this step starts from
-    for (int i = 0; i < b->n; ++i) {
-        const BatchInst& d = b->hinst[i];
-        if (d.goff[0] < 0 && d.goff[1] < 0 && d.goff[2] < 0 && d.goff[3] < 0) continue;
-        double* g[4];
-        for (int q = 0; q < 4; ++q) g[q] = d.goff[q] >= 0 ? b->gbuf + d.goff[q] : nullptr;
-        hipError_t e = launch_outflow(src + d.off, d.nx, d.ny, g, b->k, st);
+    // outflow ghosts of the state this step starts from, all instances at once
+    if (b->noflow > 0) {
+        hipLaunchKernelGGL(k_outflow_batch, dim3((unsigned)b->noflow), dim3(256), 0, st, src,
+                           b->oflow, b->inst, b->gbuf, b->k);
+        hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     BatchArgs a;
@@ -278,16 +310,12 @@ hipError_t launch_batch_step(lbm_batch* b, const double* src, double* dst, bool 
         a.m_in = b->msum + 4 * b->cells * parity;
         a.m_out = b->msum + 4 * b->cells * (1 - parity);
     } else if (V.M == PH_STATE) {
-        // state pass per instance: cell state, rest particle, energy partials
-        for (int i = 0; i < b->n; ++i) {
-            const BatchInst& d = b->hinst[i];
-            int np = 0;
-            hipError_t e = launch_state(src + d.off, dst + d.off, b->msum + d.moff,
-                                        (int64_t)d.nx * d.ny, d.ct, d.ke_axis,
-                                        ke ? b->ke_part + 2 * (int64_t)d.kp_off : nullptr, &np,
-                                        b->k, st);
-            if (e != hipSuccess) return e;
-        }
+        // state pass of every instance in one launch: cell state, rest
+        // particle, energy partials
+        hipLaunchKernelGGL(k_state_batch, dim3((unsigned)b->nblk), dim3(256), 0, st, src, dst,
+                           b->msum, b->blk_inst, b->inst, ke ? b->ke_part : nullptr, b->k);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
         a.m_in = b->msum;
     }
     a.fin = src;
@@ -498,6 +526,33 @@ static int batch_create_impl(const lbm_params* inst, int32_t n, const int64_t* f
             return bhip(e, "batch side equilibria");
         }
     }
+    // block and outflow lists of the one-launch state pass and ghost kernel
+    std::vector<int> blk;
+    std::vector<int2> ofl;
+    for (int i = 0; i < n; ++i) {
+        BatchInst& d = b->hinst[i];
+        d.blk_off = (int)blk.size();
+        const int64_t nb = ((int64_t)d.nx * d.ny + 255) / 256;
+        blk.insert(blk.end(), (size_t)nb, i);
+        for (int sd = 0; sd < 4; ++sd) {
+            if (d.goff[sd] < 0) continue;
+            const int len = sd < 2 ? d.ny : d.nx;
+            for (int q = 0; q < (len + 255) / 256; ++q) ofl.push_back(make_int2(i, sd + 4 * q));
+        }
+    }
+    b->nblk = (int)blk.size();
+    b->noflow = (int)ofl.size();
+    if ((e = hipMalloc(&b->blk_inst, sizeof(int) * blk.size())) != hipSuccess ||
+        (e = hipMemcpy(b->blk_inst, blk.data(), sizeof(int) * blk.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
+        (b->noflow > 0 &&
+         ((e = hipMalloc(&b->oflow, sizeof(int2) * ofl.size())) != hipSuccess ||
+          (e = hipMemcpy(b->oflow, ofl.data(), sizeof(int2) * ofl.size(),
+                         hipMemcpyHostToDevice)) != hipSuccess))) {
+        lbm_batch_destroy(b);
+        bhip(e, "batch block lists");
+        return LBM_ENOMEM;
+    }
     b->variant = lbmi_default_variant_cells(b->cells);
     const int rc = build_tables(b);
     if (rc) {
@@ -521,6 +576,8 @@ void lbm_batch_destroy(lbm_batch* b)
     if (b->work) hipFree(b->work);
     if (b->msum) hipFree(b->msum);
     if (b->gbuf) hipFree(b->gbuf);
+    if (b->blk_inst) hipFree(b->blk_inst);
+    if (b->oflow) hipFree(b->oflow);
     delete b;
 }
 

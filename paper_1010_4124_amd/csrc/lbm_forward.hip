@@ -46,54 +46,14 @@ void k_step(StepArgs a)
                                    a.m_out);
 }
 
-// State pass of the PH_STATE variants, one thread per cell: the moments of
-// Eq. (10) summed over the 19 planes in the order phase 1 uses, the cell
-// state (dt/tau rho, T, u/T, v/T) for the step kernel, the rest particle's
-// update (no convection: f_0' = f_0 - dt/tau (f_0 - rho F_0 (1 - u^2/2T)))
-// and per-block (sum, max) partials of rho u_n^2 / 2.
+// State pass of the PH_STATE variants, one thread per cell (state_block).
 __global__ __launch_bounds__(256) void k_state(const double* __restrict__ f,
                                                double* __restrict__ fout,
                                                double* __restrict__ st, int64_t n, double ct,
                                                int ke_axis, double* __restrict__ part, Consts k)
 {
     __shared__ double sr[8];
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    double e = 0.0;
-    if (c < n) {
-        double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
-        const double f0 = f[c];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            const double fi = f[i * n + c];
-            r += fi;
-            jx = __builtin_fma(fi, k.vx[i], jx);
-            jy = __builtin_fma(fi, k.vy[i], jy);
-            E = __builtin_fma(fi, k.hv2[i], E);
-        }
-        const CellEq q = cell_eq_from_sums(r, jx, jy, E);
-        const double F0 =
-            1.0 - 6.0 * (weight_c(k, 0, q.T) + weight_c(k, 1, q.T) + weight_c(k, 2, q.T));
-        const double fe = q.rho * F0 * q.t0;
-        fout[c] = __builtin_fma(-ct, f0 - fe, f0);
-        st[c] = ct * q.rho;
-        st[n + c] = q.T;
-        st[2 * n + c] = q.uxt;
-        st[3 * n + c] = q.uyt;
-        const double un = (ke_axis ? jx : jy) / r;
-        e = 0.5 * r * un * un;
-    }
-    if (!part) return;
-    const double s = wave_sum(e), mx = wave_max(e);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        sr[2 * w] = s;
-        sr[2 * w + 1] = mx;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = sr[0] + sr[2] + sr[4] + sr[6];
-        part[2 * blockIdx.x + 1] = fmax(fmax(sr[1], sr[3]), fmax(sr[5], sr[7]));
-    }
+    state_block(f, fout, st, n, ct, ke_axis, part, k, blockIdx.x, sr);
 }
 
 // Moment sums rho, j_x, j_y, E (Eq. (10)) per cell, in the order the step
@@ -165,39 +125,14 @@ __global__ void k_side_eq(double* out, double4 s0, double4 s1, double4 s2, doubl
     out[s * NV + i] = A * feq_poly(eta, t0);
 }
 
-// Outflow ghosts (Sec. IV.A, Eqs. (63)-(64)): for every position p along
-// an outflow side, f^eq of the moments of the nearest interior cell, into
-// g[side][i][p] (length ny for x sides, nx for y sides). blockIdx.y = side.
+// Outflow ghosts of one grid (outflow_point), blockIdx.y = side.
 __global__ __launch_bounds__(256) void k_outflow(const double* __restrict__ f, int nx, int ny,
                                                  double* g0, double* g1, double* g2, double* g3,
                                                  Consts k)
 {
     const int side = blockIdx.y;
     double* g = side == 0 ? g0 : side == 1 ? g1 : side == 2 ? g2 : g3;
-    const int len = side < 2 ? ny : nx;
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (!g || p >= len) return;
-    const int x = side == 0 ? 0 : side == 1 ? nx - 1 : p;
-    const int y = side < 2 ? p : (side == 2 ? 0 : ny - 1);
-    const int64_t n = (int64_t)nx * ny, c = (int64_t)y * nx + x;
-    double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        const double fi = f[i * n + c];
-        r += fi;
-        jx = __builtin_fma(fi, k.vx[i], jx);
-        jy = __builtin_fma(fi, k.vy[i], jy);
-        E = __builtin_fma(fi, k.hv2[i], E);
-    }
-    const CellEq q = cell_eq_from_sums(r, jx, jy, E);
-    const double F1 = weight_c(k, 0, q.T), F2 = weight_c(k, 1, q.T), F3 = weight_c(k, 2, q.T);
-    g[p] = q.rho * (1.0 - 6.0 * (F1 + F2 + F3)) * q.t0;
-#pragma unroll
-    for (int i = 1; i < NV; ++i) {
-        const double A = q.rho * (i < 7 ? F1 : i < 13 ? F2 : F3);
-        const double eta = __builtin_fma(k.vx[i], q.uxt, k.vy[i] * q.uyt);
-        g[(int64_t)i * len + p] = A * feq_poly(eta, q.t0);
-    }
+    if (g) outflow_point(f, nx, ny, g, side, blockIdx.x * 256 + threadIdx.x, k);
 }
 
 // Moments of Eq. (10) per cell.

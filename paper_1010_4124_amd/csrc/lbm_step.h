@@ -104,6 +104,89 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// Block `blk` of the state pass, one thread per cell c = blk * 256 + thread
+// of a grid of n cells: the moments of Eq. (10) summed over the 19 planes in
+// the order phase 1 uses, the cell state (dt/tau rho, T, u/T, v/T) for the
+// step kernel, the rest particle's update (no convection: f_0' = f_0 -
+// dt/tau (f_0 - rho F_0 (1 - u^2/2T))) and, if part is not null, the block's
+// (sum, max) of rho u_n^2 / 2 in part[2 blk], part[2 blk + 1]. sr: 8 doubles
+// of workgroup LDS; every thread of the block must call this.
+__device__ __forceinline__ void state_block(const double* __restrict__ f,
+                                            double* __restrict__ fout, double* __restrict__ st,
+                                            int64_t n, double ct, int ke_axis,
+                                            double* __restrict__ part, const Consts& k,
+                                            int64_t blk, double* sr)
+{
+    const int64_t c = blk * 256 + threadIdx.x;
+    double e = 0.0;
+    if (c < n) {
+        double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
+        const double f0 = f[c];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const double fi = f[i * n + c];
+            r += fi;
+            jx = __builtin_fma(fi, k.vx[i], jx);
+            jy = __builtin_fma(fi, k.vy[i], jy);
+            E = __builtin_fma(fi, k.hv2[i], E);
+        }
+        const CellEq q = cell_eq_from_sums(r, jx, jy, E);
+        const double F0 =
+            1.0 - 6.0 * (weight_c(k, 0, q.T) + weight_c(k, 1, q.T) + weight_c(k, 2, q.T));
+        const double fe = q.rho * F0 * q.t0;
+        fout[c] = __builtin_fma(-ct, f0 - fe, f0);
+        st[c] = ct * q.rho;
+        st[n + c] = q.T;
+        st[2 * n + c] = q.uxt;
+        st[3 * n + c] = q.uyt;
+        const double un = (ke_axis ? jx : jy) / r;
+        e = 0.5 * r * un * un;
+    }
+    if (!part) return;
+    const double s = wave_sum(e), mx = wave_max(e);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sr[2 * w] = s;
+        sr[2 * w + 1] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blk] = sr[0] + sr[2] + sr[4] + sr[6];
+        part[2 * blk + 1] = fmax(fmax(sr[1], sr[3]), fmax(sr[5], sr[7]));
+    }
+}
+
+// Outflow ghosts (Sec. IV.A, Eqs. (63)-(64)) at position p of side `side` of
+// an nx x ny grid: f^eq of the moments of the nearest interior cell, into
+// g[i][p] (side length ny for x sides, nx for y sides; p beyond it: nothing).
+__device__ __forceinline__ void outflow_point(const double* __restrict__ f, int nx, int ny,
+                                              double* g, int side, int p, const Consts& k)
+{
+    const int len = side < 2 ? ny : nx;
+    if (p >= len) return;
+    const int x = side == 0 ? 0 : side == 1 ? nx - 1 : p;
+    const int y = side < 2 ? p : (side == 2 ? 0 : ny - 1);
+    const int64_t n = (int64_t)nx * ny, c = (int64_t)y * nx + x;
+    double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const double fi = f[i * n + c];
+        r += fi;
+        jx = __builtin_fma(fi, k.vx[i], jx);
+        jy = __builtin_fma(fi, k.vy[i], jy);
+        E = __builtin_fma(fi, k.hv2[i], E);
+    }
+    const CellEq q = cell_eq_from_sums(r, jx, jy, E);
+    const double F1 = weight_c(k, 0, q.T), F2 = weight_c(k, 1, q.T), F3 = weight_c(k, 2, q.T);
+    g[p] = q.rho * (1.0 - 6.0 * (F1 + F2 + F3)) * q.t0;
+#pragma unroll
+    for (int i = 1; i < NV; ++i) {
+        const double A = q.rho * (i < 7 ? F1 : i < 13 ? F2 : F3);
+        const double eta = __builtin_fma(k.vx[i], q.uxt, k.vy[i] * q.uyt);
+        g[(int64_t)i * len + p] = A * feq_poly(eta, q.t0);
+    }
+}
+
 // Per-wave LDS region: the staged plane, the x flux differences, and (reused,
 // carried-moment mode only) the exchange of the 4 x R moment sums of the
 // wave's lanes.
