@@ -32,6 +32,8 @@ Other modes (for the rocprofv3 runs whose summaries live in profiles/):
   --trace-table D  per-kernel, per-grid-size durations of a rocprofv3
                    kernel trace under D, as a markdown table
   --counter-table D  the same for the counter values of one counter pass
+  --summarize-adjoint / --summarize-batch  the reverse-step and batched-sweep
+                   summaries from their traces, counter passes and run logs
 """
 from __future__ import annotations
 
@@ -360,6 +362,128 @@ def trace_table(root, match):
     print("\n".join(lines))
 
 
+def _table_rows(text):
+    """{(kernel, grid): cells} of a markdown table printed by trace_table or
+    counter_table."""
+    out = {}
+    for ln in text.strip().splitlines()[2:]:
+        c = [x.strip() for x in ln.strip("|").split("|")]
+        out[(c[0].strip("`"), int(c[1]))] = c
+    return out
+
+
+def _capture(fn, *a):
+    import contextlib
+    import io
+    buf = io.StringIO()
+    with contextlib.redirect_stdout(buf):
+        fn(*a)
+    return buf.getvalue().strip()
+
+
+def _bench_line(log_path, key):
+    with open(log_path) as fh:
+        return json.loads(next(ln for ln in fh if ln.startswith('{"%s"' % key)))[key]
+
+
+def summarize_adjoint(trace, fetch, write, log_path, commands):
+    """Markdown summary of the reverse-step profile: the kernel trace of
+    `bench.py --only adjoint` and FETCH_SIZE / WRITE_SIZE passes of
+    `bench.py --pmc-run --only adjoint --variant 3` (2048^2, (4, 18, 1, true))."""
+    k_adj, k_st = "lbmd::k_adjoint<4, 18, 1, true>", "lbmd::k_adj_state"
+    tab = _capture(trace_table, trace, ["k_adjoint", "k_adj_state"])
+    ftab = _capture(counter_table, fetch, ["k_adjoint", "k_adj_state", "copyBuffer"])
+    wtab = _capture(counter_table, write, ["k_adjoint", "k_adj_state", "copyBuffer"])
+    t, fr, wr = _table_rows(tab), _table_rows(ftab), _table_rows(wtab)
+    n = 2048 * 2048
+    # medians: the traced command also runs the overlapped gradients
+    adj, st = float(t[(k_adj, 18874368)][4]), float(t[(k_st, 4194304)][4])
+    adj256, st256 = float(t[(k_adj, 294912)][4]), float(t[(k_st, 65536)][4])
+    sf = COPY_BYTES / (float(fr[("__amd_rocclr_copyBuffer", 131072)][4]) * 1024)
+    sw = COPY_BYTES / (float(wr[("__amd_rocclr_copyBuffer", 131072)][4]) * 1024)
+    f_adj = float(fr[(k_adj, 18874368)][4]) * 1024 * sf / n
+    f_st = float(fr[(k_st, 4194304)][4]) * 1024 * sf / n
+    w_adj = float(wr[(k_adj, 18874368)][4]) * 1024 * sw / n
+    w_st = float(wr[(k_st, 4194304)][4]) * 1024 * sw / n
+    tot = f_adj + f_st + w_adj + w_st
+    ev = _bench_line(log_path, "adjoint")
+    lines = [
+        "# Reverse step (discrete adjoint), shear layer at 256^2 and 2048^2: durations and HBM traffic",
+        "",
+        "kernels: lbmd::k_adjoint<R, G, W, PS> (+ lbmd::k_adj_state for PS = true); the tuner "
+        "picks (4, 18, 1, true) or (4, 18, 2, true)",
+        "",
+        "## Kernel trace (every adjoint variant the tuner tries, per grid size)",
+        "",
+        "Grid sizes: 294912 / 18874368 work-items are the 256^2 / 2048^2 reverse steps of the "
+        "(4, 18, *) variants; 65536 / 4194304 those of the per-cell state pass.",
+        "", tab, "",
+        "Medians, since the traced command also runs the checkpointed gradients, whose reverse "
+        "steps overlap the recompute on a second stream and take longer per dispatch (they pull "
+        f"the means up). Variant (4, 18, 1, true): 2048^2 {adj:.1f} + {st:.1f} = {adj + st:.1f} us "
+        f"per reverse step, i.e. {n / (adj + st):.0f} MLUPS (the bench's events in the same run: "
+        f"{ev['reverse_step_2048']['MLUPS']:.0f}); 256^2 {adj256:.1f} + {st256:.1f} = "
+        f"{adj256 + st256:.1f} us, i.e. {65536 / (adj256 + st256):.0f} MLUPS (events: "
+        f"{ev['reverse_step_256']['MLUPS']:.0f}, with the tuner's pick of that run, "
+        f"{tuple(ev['reverse_step_256']['variant'])}).",
+        "",
+        "## Counter passes, 2048^2, variant (4, 18, 1, true), ten reverse steps",
+        "", "FETCH_SIZE (KiB per dispatch):", "", ftab, "",
+        "WRITE_SIZE (KiB per dispatch):", "", wtab, "",
+        f"Scale factors from the 512 MiB copy in the same runs: FETCH {sf:.4f}, WRITE {sw:.4f}.",
+        "",
+        "| kernel | read B/cell | written B/cell |",
+        "|---|---|---|",
+        f"| k_adjoint<4, 18, 1, true> | {f_adj:.0f} | {w_adj:.0f} |",
+        f"| k_adj_state | {f_st:.0f} | {w_st:.0f} |",
+        f"| reverse step | {f_adj + f_st:.0f} | {w_adj + w_st:.0f} |",
+        "",
+        f"Total {tot:.0f} B per cell against the algorithmic 456 (f^n and lambda^(n+1) read once, "
+        "lambda^n written once). The excess is the two-pass structure: the state pass reads f^n "
+        "and lambda^(n+1) in full and writes the four K planes and the rest plane; the plane "
+        "kernel then reads the 18 moving planes of both arrays again, with their halos, plus the "
+        f"K planes. Its {f_adj:.0f} B read per cell is close to that plane-kernel minimum "
+        "(2 x 144 + 32 = 320 B): halo rows shared by vertically adjacent tiles hit in L2. The "
+        f"state pass moves {f_st + w_st:.0f} B per cell in {st:.0f} us, "
+        f"{(f_st + w_st) * n / st / 1e3:.0f} GB/s.",
+        "",
+        "Commands (repository root, TMPDIR=/tmp):",
+    ] + ["    " + c for c in commands]
+    print("\n".join(lines))
+
+
+def summarize_batch(trace, log_path, commands):
+    """Markdown summary of the batched sweep's kernel trace
+    (`bench.py --only batch --batch-variant V`)."""
+    tab = _capture(trace_table, trace, ["k_step_batch", "k_reduce_batch"])
+    rows = _table_rows(tab)
+    ev = _bench_line(log_path, "batch")
+    v = ev["variant"]
+    name = (f"lbmd::k_step_batch<{v[0]}, {v[1]}, {v[2]}, {v[3]}, "
+            f"{'true' if v[4] else 'false'}, {v[5]}>")
+    step_key = max((k for k in rows if k[0] == name), key=lambda k: int(rows[k][2]))
+    red_key = next(k for k in rows if k[0] == "lbmd::k_reduce_batch")
+    stp, red = float(rows[step_key][3]), float(rows[red_key][3])
+    cells = ev["cells"]
+    lines = [
+        f"# Batched step, 64-instance shear-layer sweep ({cells} cells): kernel durations",
+        "",
+        "The sweep's instances (seed 2024) have sizes drawn from {128, 192, 256, 384, 512}^2; one "
+        "launch of lbmd::k_step_batch advances all of them by one step, and "
+        "lbmd::k_reduce_batch turns the per-tile partials into the 64 energy-log entries. The "
+        f"step variant is fixed to {tuple(v)}, the one the bench's tuner picks for this sweep "
+        "(the tuner's own short trials run perturbed under the tracer), with one workgroup per "
+        f"work item ({step_key[1]} work-items).",
+        "", tab, "",
+        f"Per step: {stp:.1f} + {red:.1f} = {stp + red:.1f} us, i.e. {cells / (stp + red):.0f} "
+        f"MLUPS; the bench's events in the same run ({ev['steps']} steps, graph chunks of "
+        f"{ev['graph_chunk']}) gave {ev['MLUPS']:.0f} MLUPS.",
+        "",
+        "Command (repository root, TMPDIR=/tmp):",
+    ] + ["    " + c for c in commands]
+    print("\n".join(lines))
+
+
 def counter_table(root, match):
     """Markdown table of one rocprofv3 counter pass: the mean value per
     dispatch of each counter, grouped by kernel and grid size (FETCH_SIZE
@@ -526,6 +650,8 @@ def main():
     ap.add_argument("--trace-table", metavar="TRACE")
     ap.add_argument("--counter-table", metavar="PMC")
     ap.add_argument("--match", nargs="*", default=[])
+    ap.add_argument("--summarize-adjoint", nargs=4, metavar=("TRACE", "FETCH", "WRITE", "LOG"))
+    ap.add_argument("--summarize-batch", nargs=2, metavar=("TRACE", "LOG"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: one GPU only; --gpus {args.gpus} is not supported. The step shards by "
@@ -540,6 +666,12 @@ def main():
         return
     if args.counter_table:
         counter_table(args.counter_table, args.match)
+        return
+    if args.summarize_adjoint:
+        summarize_adjoint(*args.summarize_adjoint, args.commands or [])
+        return
+    if args.summarize_batch:
+        summarize_batch(*args.summarize_batch, args.commands or [])
         return
 
     import torch

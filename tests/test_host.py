@@ -178,3 +178,21 @@ def test_trace_table_groups_by_kernel_and_grid(tmp_path, capsys):
     assert len(out) == 4 and "k_init" not in "".join(out)
     assert out[2] == "| `lbmd::k_adjoint<4, 18, 1, true>` | 2048 | 2 | 2.00 | 2.00 |"
     assert out[3] == "| `lbmd::k_adjoint<4, 18, 1, true>` | 65536 | 1 | 8.00 | 8.00 |"
+
+
+def test_batch_summary_from_trace_and_log(tmp_path, capsys):
+    d = tmp_path / "tr"
+    d.mkdir()
+    k = '"lbmd::k_step_batch<4, 1, 2, 2, true, 1>(lbmd::BatchArgs)"'
+    rows = [f"KERNEL_DISPATCH,{k},0,530000,1329152", f"KERNEL_DISPATCH,{k},0,534000,1329152",
+            'KERNEL_DISPATCH,"lbmd::k_reduce_batch(double const*)",0,5000,16384']
+    (d / "t_kernel_trace.csv").write_text("Kind,Kernel_Name,Start_Timestamp,End_Timestamp,"
+                                          "Grid_Size_X\n" + "\n".join(rows) + "\n")
+    log = tmp_path / "run.log"
+    log.write_text('W noise\n{"batch": {"instances": 64, "cells": 5316608, "steps": 2000, '
+                   '"MLUPS": 9900.0, "variant": [4, 1, 2, 2, 1, 1], "graph_chunk": 100}}\n')
+    bench.summarize_batch(str(d), str(log), ["cmd"])
+    out = capsys.readouterr().out
+    # 532 + 5 us per step over 5316608 cells
+    assert "532.0 + 5.0 = 537.0 us, i.e. 9901 MLUPS" in out and "gave 9900 MLUPS" in out
+    assert out.rstrip().endswith("    cmd")
