@@ -138,11 +138,11 @@ __global__ __launch_bounds__(256) void k_outflow_batch(const double* __restrict_
 __global__ __launch_bounds__(256) void k_reduce_batch(const double* __restrict__ part,
                                                       const BatchInst* __restrict__ inst,
                                                       double* __restrict__ out, int64_t stride,
-                                                      int64_t pos)
+                                                      int64_t pos, int64_t row_stride)
 {
     __shared__ double sr[8];
     const BatchInst& d = inst[blockIdx.x];
-    const double* p = part + 2 * (int64_t)d.kp_off;
+    const double* p = part + blockIdx.y * row_stride + 2 * (int64_t)d.kp_off;
     double s = 0.0, mx = 0.0;
     for (int j = threadIdx.x; j < d.kp_n; j += 256) {
         s += p[2 * j];
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const double* __restrict__
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double* o = out + blockIdx.x * stride + pos;
+        double* o = out + blockIdx.x * stride + pos + 2 * blockIdx.y;
         o[0] = (sr[0] + sr[2] + sr[4] + sr[6]) * d.dxdy;
         o[1] = fmax(fmax(sr[1], sr[3]), fmax(sr[5], sr[7]));
     }
@@ -197,8 +197,9 @@ struct lbm_batch {
     BatchInst* inst = nullptr;
     int2* work = nullptr;
     int work_cap = 0, ke_cap = 0;
+    int ke_rows = 1;  // rows of ke_part: steps of a graph whose energy partials one launch reduces
     double* scratch = nullptr;
-    double* ke_part = nullptr;
+    double* ke_part = nullptr;  // [ke_rows][ke_cap][2] energy partials
     double* ke_ring = nullptr;  // [n][graph_chunk][2]
     double* msum = nullptr;     // 2 x (4 * cells): carried moment sums, ping-pong
     double* gbuf = nullptr;     // outflow ghost arrays of the instances that have them
@@ -290,10 +291,12 @@ int build_tables(lbm_batch* b)
     return LBM_OK;
 }
 
-// Step s of a call reads moment set s % 2 and writes the other one.
+// Step s of a call reads moment set s % 2 and writes the other one; its
+// energy partials (ke) go to row `row` of ke_part.
 hipError_t launch_batch_step(lbm_batch* b, const double* src, double* dst, bool ke, int parity,
-                             hipStream_t st)
+                             hipStream_t st, int row = 0)
 {
+    double* part = b->ke_part + 2 * (int64_t)b->ke_cap * row;
     const BatchVariant& V = kBatchVariants[b->variant];
     // outflow ghosts of the state this step starts from, all instances at once
     if (b->noflow > 0) {
@@ -313,14 +316,14 @@ hipError_t launch_batch_step(lbm_batch* b, const double* src, double* dst, bool 
         // state pass of every instance in one launch: cell state, rest
         // particle, energy partials
         hipLaunchKernelGGL(k_state_batch, dim3((unsigned)b->nblk), dim3(256), 0, st, src, dst,
-                           b->msum, b->blk_inst, b->inst, ke ? b->ke_part : nullptr, b->k);
+                           b->msum, b->blk_inst, b->inst, ke ? part : nullptr, b->k);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         a.m_in = b->msum;
     }
     a.fin = src;
     a.fout = dst;
-    a.ke_part = ke && V.M != PH_STATE ? b->ke_part : nullptr;
+    a.ke_part = ke && V.M != PH_STATE ? part : nullptr;
     a.inst = b->inst;
     a.work = b->work;
     a.nwork = b->nwork;
@@ -332,11 +335,13 @@ hipError_t launch_batch_step(lbm_batch* b, const double* src, double* dst, bool 
     return hipGetLastError();
 }
 
+// Energy-log entries of `rows` consecutive steps (rows 0..rows-1 of ke_part)
+// for every instance: out[i * stride + pos + 2 r].
 hipError_t launch_batch_reduce(lbm_batch* b, double* out, int64_t stride, int64_t pos,
-                               hipStream_t st)
+                               hipStream_t st, int rows = 1)
 {
-    hipLaunchKernelGGL(k_reduce_batch, dim3(b->n), dim3(256), 0, st, b->ke_part, b->inst, out,
-                       stride, pos);
+    hipLaunchKernelGGL(k_reduce_batch, dim3(b->n, rows), dim3(256), 0, st, b->ke_part, b->inst,
+                       out, stride, pos, 2 * (int64_t)b->ke_cap);
     return hipGetLastError();
 }
 
@@ -376,8 +381,12 @@ int get_graph(lbm_batch* b, const double* x, double* y, bool ke, hipGraphExec_t*
     for (int s = 0; s < b->graph_chunk && le == hipSuccess; ++s) {
         const double* src = (s % 2 == 0) ? x : y;
         double* dst = (s % 2 == 0) ? y : (double*)x;
-        le = launch_batch_step(b, src, dst, ke, (1 + s) % 2, b->cap);
-        if (le == hipSuccess && ke) le = launch_batch_reduce(b, b->ke_ring, 2 * b->graph_chunk, 2 * s, b->cap);
+        // energy partials of up to ke_rows steps, reduced by one node
+        const int row = s % b->ke_rows;
+        le = launch_batch_step(b, src, dst, ke, (1 + s) % 2, b->cap, row);
+        if (le == hipSuccess && ke && (row == b->ke_rows - 1 || s == b->graph_chunk - 1))
+            le = launch_batch_reduce(b, b->ke_ring, 2 * b->graph_chunk, 2 * (s - row), b->cap,
+                                     row + 1);
     }
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(b->cap, &graph);
@@ -482,9 +491,13 @@ static int batch_create_impl(const lbm_params* inst, int32_t n, const int64_t* f
     b->gcap = gtotal;
     b->work_cap = (int)wmax;
     b->ke_cap = (int)std::max<int64_t>(tmax, 2 * NV);
+    // rows of partials for graph steps: up to 32, within 64 MiB
+    b->ke_rows = (int)std::max<int64_t>(
+        1, std::min<int64_t>(32, (int64_t)(64 << 20) / (16 * (int64_t)b->ke_cap)));
     b->hinst.resize(n);
     if ((e = hipMalloc(&b->scratch, sizeof(double) * (size_t)b->f_extent)) != hipSuccess ||
-        (e = hipMalloc(&b->ke_part, sizeof(double) * 2 * (size_t)b->ke_cap)) != hipSuccess ||
+        (e = hipMalloc(&b->ke_part, sizeof(double) * 2 * (size_t)b->ke_cap * b->ke_rows)) !=
+            hipSuccess ||
         (e = hipMalloc(&b->inst, sizeof(BatchInst) * (size_t)n)) != hipSuccess ||
         (e = hipMalloc(&b->work, sizeof(int2) * (size_t)b->work_cap)) != hipSuccess ||
         (e = hipMalloc(&b->msum, sizeof(double) * 8 * (size_t)b->cells)) != hipSuccess ||
