@@ -274,8 +274,9 @@ int lbm_step(lbm_ctx* c, const double* f_in, double* f_out, int32_t nsteps, doub
         const double* m_in = nullptr;
         double* m_out = nullptr;
         int nparts = ntiles;
-        if (c->gb[0] || c->gb[1] || c->gb[2] || c->gb[3]) {
-            // outflow ghosts of the state this step starts from
+        if ((c->gb[0] || c->gb[1] || c->gb[2] || c->gb[3]) && mode != 2) {
+            // outflow ghosts of the state this step starts from (the state
+            // pass writes them itself)
             hipError_t e = launch_outflow(src, p.nx, p.ny, c->gb, c->k, st);
             if (e != hipSuccess) return hip_fail(e, "lbm_step outflow");
         }
@@ -284,8 +285,8 @@ int lbm_step(lbm_ctx* c, const double* f_in, double* f_out, int32_t nsteps, doub
             m_out = c->msum + 4 * n * ((s + 1) % 2);
         } else if (mode == 2) {
             // state pass: cell state, rest particle and energy partials
-            hipError_t e = launch_state(src, dst, c->msum, n, ct, p.ke_axis,
-                                        ke_log ? ke_row(c, s) : nullptr, &nparts, c->k, st);
+            hipError_t e = launch_state(src, dst, c->msum, p.nx, p.ny, ct, p.ke_axis,
+                                        ke_log ? ke_row(c, s) : nullptr, &nparts, c->k, c->gb, st);
             if (e != hipSuccess) return hip_fail(e, "lbm_step state");
             m_in = c->msum;
         }

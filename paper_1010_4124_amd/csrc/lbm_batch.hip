@@ -106,19 +106,26 @@ void k_step_batch(BatchArgs a)
 // out[i * stride + pos + {0, 1}] = (dxdy * sum, max).
 // State pass of a batch in one launch: block b is block b - blk_off of the
 // instance blk_inst[b] (state_block; its energy partial lands at global
-// block b, where the instance's kp_off points for the state-pass variants).
+// block b, where the instance's kp_off points for the state-pass variants;
+// cells on outflow sides also write the instance's ghost values).
 __global__ __launch_bounds__(256) void k_state_batch(const double* __restrict__ fin,
                                                      double* __restrict__ fout,
                                                      double* __restrict__ msum,
                                                      const int* __restrict__ blk_inst,
                                                      const BatchInst* __restrict__ inst,
-                                                     double* __restrict__ ke_part, Consts k)
+                                                     double* __restrict__ ke_part, double* gbuf,
+                                                     Consts k)
 {
     __shared__ double sr[8];
     const BatchInst& d = inst[blk_inst[blockIdx.x]];
+    Ghosts gh;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) gh.g[q] = d.goff[q] >= 0 ? gbuf + d.goff[q] : nullptr;
+    gh.nx = d.nx;
+    gh.ny = d.ny;
     state_block(fin + d.off, fout + d.off, msum + d.moff, (int64_t)d.nx * d.ny, d.ct, d.ke_axis,
                 ke_part ? ke_part + 2 * (int64_t)d.blk_off : nullptr, k,
-                (int64_t)blockIdx.x - d.blk_off, sr);
+                (int64_t)blockIdx.x - d.blk_off, sr, gh);
 }
 
 // Outflow ghosts of every outflow side of a batch in one launch: entry b of
@@ -298,8 +305,9 @@ hipError_t launch_batch_step(lbm_batch* b, const double* src, double* dst, bool 
 {
     double* part = b->ke_part + 2 * (int64_t)b->ke_cap * row;
     const BatchVariant& V = kBatchVariants[b->variant];
-    // outflow ghosts of the state this step starts from, all instances at once
-    if (b->noflow > 0) {
+    // outflow ghosts of the state this step starts from, all instances at
+    // once (with a state pass, that pass writes them)
+    if (b->noflow > 0 && V.M != PH_STATE) {
         hipLaunchKernelGGL(k_outflow_batch, dim3((unsigned)b->noflow), dim3(256), 0, st, src,
                            b->oflow, b->inst, b->gbuf, b->k);
         hipError_t e = hipGetLastError();
@@ -316,7 +324,7 @@ hipError_t launch_batch_step(lbm_batch* b, const double* src, double* dst, bool 
         // state pass of every instance in one launch: cell state, rest
         // particle, energy partials
         hipLaunchKernelGGL(k_state_batch, dim3((unsigned)b->nblk), dim3(256), 0, st, src, dst,
-                           b->msum, b->blk_inst, b->inst, ke ? part : nullptr, b->k);
+                           b->msum, b->blk_inst, b->inst, ke ? part : nullptr, b->gbuf, b->k);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         a.m_in = b->msum;

@@ -50,10 +50,11 @@ void k_step(StepArgs a)
 __global__ __launch_bounds__(256) void k_state(const double* __restrict__ f,
                                                double* __restrict__ fout,
                                                double* __restrict__ st, int64_t n, double ct,
-                                               int ke_axis, double* __restrict__ part, Consts k)
+                                               int ke_axis, double* __restrict__ part, Consts k,
+                                               Ghosts gh)
 {
     __shared__ double sr[8];
-    state_block(f, fout, st, n, ct, ke_axis, part, k, blockIdx.x, sr);
+    state_block(f, fout, st, n, ct, ke_axis, part, k, blockIdx.x, sr, gh);
 }
 
 // Moment sums rho, j_x, j_y, E (Eq. (10)) per cell, in the order the step
@@ -292,13 +293,19 @@ hipError_t launch_outflow(const double* f, int nx, int ny, double* const g[4], c
     return hipGetLastError();
 }
 
-hipError_t launch_state(const double* f, double* fout, double* state, int64_t n, double ct,
-                        int ke_axis, double* part, int* nparts, const Consts& k, hipStream_t st)
+hipError_t launch_state(const double* f, double* fout, double* state, int nx, int ny, double ct,
+                        int ke_axis, double* part, int* nparts, const Consts& k,
+                        double* const gb[4], hipStream_t st)
 {
+    const int64_t n = (int64_t)nx * ny;
     const int64_t blocks = (n + 255) / 256;
     *nparts = (int)blocks;
+    Ghosts gh;
+    for (int q = 0; q < 4; ++q) gh.g[q] = gb ? gb[q] : nullptr;
+    gh.nx = nx;
+    gh.ny = ny;
     hipLaunchKernelGGL(k_state, dim3((unsigned)blocks), dim3(256), 0, st, f, fout, state, n, ct,
-                       ke_axis, part, k);
+                       ke_axis, part, k, gh);
     return hipGetLastError();
 }
 

@@ -46,8 +46,9 @@ hipError_t launch_step_lo(int scheme, const double* fin, double* fout, const Con
 hipError_t launch_outflow(const double* f, int nx, int ny, double* const g[4], const Consts& k,
                           hipStream_t st);
 hipError_t launch_sums(const double* f, double* m, const Consts& k, int64_t n, hipStream_t st);
-hipError_t launch_state(const double* f, double* fout, double* state, int64_t n, double ct,
-                        int ke_axis, double* part, int* nparts, const Consts& k, hipStream_t st);
+hipError_t launch_state(const double* f, double* fout, double* state, int nx, int ny, double ct,
+                        int ke_axis, double* part, int* nparts, const Consts& k,
+                        double* const gb[4], hipStream_t st);
 hipError_t launch_reduce_pairs(const double* part, int n, int rows, int64_t stride, double dxdy,
                                double* out2, hipStream_t st);
 hipError_t launch_init(const double* rho, const double* ux, const double* uy, const double* T,

@@ -104,18 +104,41 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// Outflow ghost arrays of a grid (null: not an outflow side) and its shape.
+struct Ghosts {
+    double* g[4];
+    int nx, ny;
+};
+
+// f^eq of cell state q into position p of the ghost array g of a side of
+// length len (g[i * len + p]), evaluated as outflow_point evaluates it.
+__device__ __forceinline__ void ghost_from_state(double* g, int len, int p, const CellEq& q,
+                                                 const Consts& k)
+{
+    const double F1 = weight_c(k, 0, q.T), F2 = weight_c(k, 1, q.T), F3 = weight_c(k, 2, q.T);
+    g[p] = q.rho * (1.0 - 6.0 * (F1 + F2 + F3)) * q.t0;
+#pragma unroll
+    for (int i = 1; i < NV; ++i) {
+        const double A = q.rho * (i < 7 ? F1 : i < 13 ? F2 : F3);
+        const double eta = __builtin_fma(k.vx[i], q.uxt, k.vy[i] * q.uyt);
+        g[(int64_t)i * len + p] = A * feq_poly(eta, q.t0);
+    }
+}
+
 // Block `blk` of the state pass, one thread per cell c = blk * 256 + thread
 // of a grid of n cells: the moments of Eq. (10) summed over the 19 planes in
 // the order phase 1 uses, the cell state (dt/tau rho, T, u/T, v/T) for the
 // step kernel, the rest particle's update (no convection: f_0' = f_0 -
 // dt/tau (f_0 - rho F_0 (1 - u^2/2T))) and, if part is not null, the block's
-// (sum, max) of rho u_n^2 / 2 in part[2 blk], part[2 blk + 1]. sr: 8 doubles
-// of workgroup LDS; every thread of the block must call this.
+// (sum, max) of rho u_n^2 / 2 in part[2 blk], part[2 blk + 1]. Cells on an
+// outflow side (gh.g[side] not null) also write their ghost values, as the
+// outflow kernel would from the same f (Eqs. (63)-(64)). sr: 8 doubles of
+// workgroup LDS; every thread of the block must call this.
 __device__ __forceinline__ void state_block(const double* __restrict__ f,
                                             double* __restrict__ fout, double* __restrict__ st,
                                             int64_t n, double ct, int ke_axis,
                                             double* __restrict__ part, const Consts& k,
-                                            int64_t blk, double* sr)
+                                            int64_t blk, double* sr, const Ghosts& gh)
 {
     const int64_t c = blk * 256 + threadIdx.x;
     double e = 0.0;
@@ -141,6 +164,13 @@ __device__ __forceinline__ void state_block(const double* __restrict__ f,
         st[3 * n + c] = q.uyt;
         const double un = (ke_axis ? jx : jy) / r;
         e = 0.5 * r * un * un;
+        if (gh.g[0] || gh.g[1] || gh.g[2] || gh.g[3]) {
+            const int y = (int)(c / gh.nx), x = (int)(c - (int64_t)y * gh.nx);
+            if (gh.g[0] && x == 0) ghost_from_state(gh.g[0], gh.ny, y, q, k);
+            if (gh.g[1] && x == gh.nx - 1) ghost_from_state(gh.g[1], gh.ny, y, q, k);
+            if (gh.g[2] && y == 0) ghost_from_state(gh.g[2], gh.nx, x, q, k);
+            if (gh.g[3] && y == gh.ny - 1) ghost_from_state(gh.g[3], gh.nx, x, q, k);
+        }
     }
     if (!part) return;
     const double s = wave_sum(e), mx = wave_max(e);
@@ -176,15 +206,7 @@ __device__ __forceinline__ void outflow_point(const double* __restrict__ f, int 
         jy = __builtin_fma(fi, k.vy[i], jy);
         E = __builtin_fma(fi, k.hv2[i], E);
     }
-    const CellEq q = cell_eq_from_sums(r, jx, jy, E);
-    const double F1 = weight_c(k, 0, q.T), F2 = weight_c(k, 1, q.T), F3 = weight_c(k, 2, q.T);
-    g[p] = q.rho * (1.0 - 6.0 * (F1 + F2 + F3)) * q.t0;
-#pragma unroll
-    for (int i = 1; i < NV; ++i) {
-        const double A = q.rho * (i < 7 ? F1 : i < 13 ? F2 : F3);
-        const double eta = __builtin_fma(k.vx[i], q.uxt, k.vy[i] * q.uyt);
-        g[(int64_t)i * len + p] = A * feq_poly(eta, q.t0);
-    }
+    ghost_from_state(g, len, p, cell_eq_from_sums(r, jx, jy, E), k);
 }
 
 // Per-wave LDS region: the staged plane, the x flux differences, and (reused,
