@@ -167,7 +167,7 @@ def bench_forward_large(args):
     big = inputs.khi(2048, 2048, dx=1e-3, dy=1e-3, dt=1e-5, tau=1e-5, Dv=0.01, Drho=0.04)
     ctx = lbm.Context.from_setup(big)
     f0 = ctx.init(*big.fields())
-    tune.tune_context(ctx, f0, nsteps=10, use_cache=False)
+    tune.tune_context(ctx, f0, nsteps=30, use_cache=False)
     out = ctx.empty_f()
     ctx.step(f0, 10, out=out)
     secs, _ = sync_time(lambda: ctx.step(f0, args.large_steps, out=out))
