@@ -197,3 +197,11 @@ def test_batch_summary_from_trace_and_log(tmp_path, capsys):
     assert "532.0 us for the step kernel and 2.50 us" in out
     assert "534.5 us in all, i.e. 9947 MLUPS" in out and "gave 9900 MLUPS" in out
     assert out.rstrip().endswith("    cmd")
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU only" in r.stderr and r.stdout == ""
