@@ -45,7 +45,9 @@ enum {
     LBM_EINVAL = -1,       /* bad argument: null pointer, sizes, aliasing, parameters */
     LBM_EUNSUPPORTED = -2, /* valid request the library does not implement */
     LBM_EHIP = -3,         /* HIP runtime error (message in lbm_last_error) */
-    LBM_ENOMEM = -4        /* device allocation failed */
+    LBM_ENOMEM = -4,       /* device allocation failed */
+    LBM_ENONFINITE = -5,   /* lbm_check_state: a NaN or infinity in the state */
+    LBM_ENONPHYS = -6      /* lbm_check_state: a cell with rho <= 0 or T <= 0 */
 };
 
 /* Boundary treatment of one side. */
@@ -131,6 +133,19 @@ int lbm_moments(lbm_ctx* ctx, const double* f, double* rho, double* ux, double* 
  * rho u_n^2 / 2 of f (device double[2]); u_n is u_y, or u_x when
  * ke_axis = 1 (as in every energy log below). */
 int lbm_kinetic_y(lbm_ctx* ctx, const double* f, double* out2, lbm_stream stream);
+
+/* Sanity check of a state: per cell, the moments of Eq. (10) must be finite
+ * and describe a gas, rho > 0 and T > 0 (the weights F_k(T) of Eqs. (44)-(46)
+ * and the equilibrium of Eq. (28) divide by rho and T; an explicit step that
+ * has gone unstable shows here first). A cell is non-finite if one of its 19
+ * values or its (rho, u, T) is a NaN or an infinity, and non-physical if all
+ * are finite but rho <= 0 or T <= 0. f: one 19-plane field. out4: NULL or host
+ * int64[4] = (non-finite cells, non-physical cells, index y*nx + x of the
+ * first non-finite cell or -1, of the first non-physical cell or -1).
+ * Synchronous: waits for the check on `stream`. Returns LBM_ENONFINITE if any
+ * cell is non-finite, else LBM_ENONPHYS if any is non-physical, else LBM_OK
+ * (LBM_EINVAL, LBM_EHIP as usual); the message names the first such cell. */
+int lbm_check_state(lbm_ctx* ctx, const double* f, int64_t* out4, lbm_stream stream);
 
 /* Discrete adjoint of one step (reverse mode of lbm_step with nsteps = 1):
  *   lam_n = (dS/df)^T lam_np1 + w dE_y/df,   S = the step of Eq. (47),

@@ -25,24 +25,35 @@ PERIODIC, FIXED_EQ, REFLECT, OUTFLOW = 0, 1, 2, 3
 NV = 19
 
 __all__ = [
-    "OracleParams", "build_oracle", "lib", "velocity_table", "weights", "feq_cell",
+    "OracleParams", "build_oracle", "lib", "lib_contracted", "velocity_table", "weights", "feq_cell",
     "moments_cell", "weno5", "weno5_grad", "weno_periodic_line", "scheme_periodic_line",
-    "init", "moments",
+    "init", "moments", "state_check",
     "step", "kinetic_y", "kinetic_y_grad", "adjoint_step", "init_vjp", "feq_partials",
     "PERIODIC", "FIXED_EQ", "REFLECT", "OUTFLOW", "NV",
 ]
 
 
-def build_oracle(force: bool = False) -> str:
-    """Compile the oracle with gcc: -O2, no FMA contraction, no fast-math."""
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
-        return LIB
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+# The same source built with fused multiply-adds allowed (-mfma
+# -ffp-contract=fast): every expression then rounds once per fused pair
+# instead of once per operation. Its arithmetic is the oracle's; it exists to
+# measure how far two legal roundings of the same scheme drift apart over a
+# long run (the rounding-accumulation reading of the long-run parity bar).
+LIB_FMA = os.path.join(HERE, "liblbm_oracle_fma.so")
+
+
+def build_oracle(force: bool = False, contract: bool = False) -> str:
+    """Compile the oracle with gcc: -O2, no FMA contraction, no fast-math
+    (contract=True: the FMA-contracted build, LIB_FMA)."""
+    out = LIB_FMA if contract else LIB
+    if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(SRC):
+        return out
+    tmp = out + ".tmp%d" % os.getpid()
+    fp = ["-mfma", "-ffp-contract=fast"] if contract else ["-ffp-contract=off"]
+    cmd = ["gcc", "-O2", *fp, "-fno-fast-math", "-fopenmp", "-fPIC",
            "-shared", "-std=c11", "-Wall", "-Wno-unused-function", SRC, "-o", tmp, "-lm"]
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 class OracleParams(C.Structure):
@@ -75,41 +86,55 @@ class OracleParams(C.Structure):
 
 
 _lib = None
+_lib_fma = None
+
+
+def lib_contracted():
+    """The FMA-contracted build (LIB_FMA), with the same entry points."""
+    global _lib_fma
+    if _lib_fma is None:
+        _lib_fma = _bind(C.CDLL(build_oracle(contract=True)))
+    return _lib_fma
 
 
 def lib():
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build_oracle())
-        d = C.c_double
-        pd = C.POINTER(C.c_double)
-        pi = C.POINTER(C.c_int32)
-        pp = C.POINTER(OracleParams)
-        _lib.orc_velocity_table.argtypes = [pd, pd, pd, pd, pi, pi, pi]
-        _lib.orc_weights.argtypes = [d, pd, pd]
-        _lib.orc_weights.restype = None
-        _lib.orc_feq_cell.argtypes = [d, d, d, d, pd, pd]
-        _lib.orc_feq_cell.restype = None
-        _lib.orc_moments_cell.argtypes = [pd, pd, pd]
-        _lib.orc_moments_cell.restype = None
-        _lib.orc_weno5.argtypes = [d, d, d, d, d, d]
-        _lib.orc_weno5.restype = d
-        _lib.orc_weno5_grad.argtypes = [d, d, d, d, d, d, pd]
-        _lib.orc_weno5_grad.restype = None
-        _lib.orc_weno_periodic_line.argtypes = [pd, C.c_int, C.c_int, d, pd]
-        _lib.orc_weno_periodic_line.restype = None
-        _lib.orc_scheme_periodic_line.argtypes = [pd, C.c_int, C.c_int, C.c_int, d, pd]
-        _lib.orc_scheme_periodic_line.restype = None
-        _lib.orc_init.argtypes = [pp, pd, pd, pd, pd, pd]
-        _lib.orc_moments.argtypes = [pp, pd, pd, pd, pd, pd]
-        _lib.orc_step.argtypes = [pp, pd, pd, C.c_int, C.c_int]
-        _lib.orc_kinetic_y.argtypes = [pp, pd, pd]
-        _lib.orc_kinetic_y_grad.argtypes = [pp, pd, pd]
-        _lib.orc_adjoint_step.argtypes = [pp, pd, pd, d, pd]
-        _lib.orc_init_vjp.argtypes = [pp, pd, pd, pd, pd, pd, pd, pd, pd, pd]
-        _lib.orc_feq_partials.argtypes = [d, d, d, d, pd, C.c_int, pd]
-        _lib.orc_feq_partials.restype = None
+        _lib = _bind(C.CDLL(build_oracle()))
     return _lib
+
+
+def _bind(L):
+    """Declare the entry points' signatures on a loaded oracle build."""
+    d = C.c_double
+    pd = C.POINTER(C.c_double)
+    pi = C.POINTER(C.c_int32)
+    pp = C.POINTER(OracleParams)
+    L.orc_velocity_table.argtypes = [pd, pd, pd, pd, pi, pi, pi]
+    L.orc_weights.argtypes = [d, pd, pd]
+    L.orc_weights.restype = None
+    L.orc_feq_cell.argtypes = [d, d, d, d, pd, pd]
+    L.orc_feq_cell.restype = None
+    L.orc_moments_cell.argtypes = [pd, pd, pd]
+    L.orc_moments_cell.restype = None
+    L.orc_weno5.argtypes = [d, d, d, d, d, d]
+    L.orc_weno5.restype = d
+    L.orc_weno5_grad.argtypes = [d, d, d, d, d, d, pd]
+    L.orc_weno5_grad.restype = None
+    L.orc_weno_periodic_line.argtypes = [pd, C.c_int, C.c_int, d, pd]
+    L.orc_weno_periodic_line.restype = None
+    L.orc_scheme_periodic_line.argtypes = [pd, C.c_int, C.c_int, C.c_int, d, pd]
+    L.orc_scheme_periodic_line.restype = None
+    L.orc_init.argtypes = [pp, pd, pd, pd, pd, pd]
+    L.orc_moments.argtypes = [pp, pd, pd, pd, pd, pd]
+    L.orc_step.argtypes = [pp, pd, pd, C.c_int, C.c_int]
+    L.orc_kinetic_y.argtypes = [pp, pd, pd]
+    L.orc_kinetic_y_grad.argtypes = [pp, pd, pd]
+    L.orc_adjoint_step.argtypes = [pp, pd, pd, d, pd]
+    L.orc_init_vjp.argtypes = [pp, pd, pd, pd, pd, pd, pd, pd, pd, pd]
+    L.orc_feq_partials.argtypes = [d, d, d, d, pd, C.c_int, pd]
+    L.orc_feq_partials.restype = None
+    return L
 
 
 def _p(a):
@@ -211,11 +236,30 @@ def moments(params, f):
     return tuple(out)
 
 
-def step(params, f, nsteps=1, nthreads=1):
+def state_check(params, f):
+    """Classify the cells of f as the state check does: non-finite if one of
+    its 19 values or its moments (Eq. (10)) is not finite, non-physical if all
+    are finite but rho <= 0 or T <= 0. Returns (non-finite cells,
+    non-physical cells, first non-finite cell index y*nx + x or -1, first
+    non-physical cell or -1)."""
+    f = _f64(f)
+    with np.errstate(all="ignore"):
+        rho, ux, uy, T = moments(params, f)
+        fin = np.isfinite(f).all(axis=0)
+        for q in (rho, ux, uy, T):
+            fin &= np.isfinite(q)
+        bad = ~fin
+        unphys = fin & ~((rho > 0.0) & (T > 0.0))
+    first = [int(np.flatnonzero(m.ravel())[0]) if m.any() else -1 for m in (bad, unphys)]
+    return int(bad.sum()), int(unphys.sum()), first[0], first[1]
+
+
+def step(params, f, nsteps=1, nthreads=1, contracted=False):
+    """nsteps forward steps; contracted=True runs the FMA-contracted build."""
     f = _f64(f)
     out = np.zeros_like(f)
-    _check(lib().orc_step(C.byref(params), _p(f), _p(out), int(nsteps), int(nthreads)),
-           "step")
+    L = lib_contracted() if contracted else lib()
+    _check(L.orc_step(C.byref(params), _p(f), _p(out), int(nsteps), int(nthreads)), "step")
     return out
 
 

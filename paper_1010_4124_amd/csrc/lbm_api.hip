@@ -150,7 +150,8 @@ int lbm_create(const lbm_params* p, lbm_ctx** out)
         (e = hipMalloc(&c->colbuf, (size_t)p->nx * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&c->msum, 8 * n * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&c->gbuf, NV * 2 * ((size_t)p->nx + p->ny) * sizeof(double))) !=
-            hipSuccess) {
+            hipSuccess ||
+        (e = hipMalloc(&c->chk, 4 * sizeof(unsigned long long))) != hipSuccess) {
         lbm_destroy(c);
         hip_fail(e, "hipMalloc");
         return LBM_ENOMEM;
@@ -185,6 +186,7 @@ void lbm_destroy(lbm_ctx* c)
     if (c->colbuf) hipFree(c->colbuf);
     if (c->msum) hipFree(c->msum);
     if (c->gbuf) hipFree(c->gbuf);
+    if (c->chk) hipFree(c->chk);
     delete c;
 }
 
@@ -322,6 +324,38 @@ int lbm_kinetic_y(lbm_ctx* c, const double* f, double* out2, lbm_stream stream)
     hipError_t e = launch_kinetic_part(f, c->k, n, c->p.ke_axis, c->ke_part, &np, st);
     if (e == hipSuccess) e = launch_reduce_pairs(c->ke_part, np, 1, 0, c->p.dx * c->p.dy, out2, st);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_kinetic_y");
+}
+
+int lbm_check_state(lbm_ctx* c, const double* f, int64_t* out4, lbm_stream stream)
+{
+    if (!c || !f) return fail(LBM_EINVAL, "null argument%s%lld");
+    const int64_t n = (int64_t)c->p.nx * c->p.ny;
+    hipStream_t st = (hipStream_t)stream;
+    unsigned long long h[4];
+    hipError_t e = launch_check(f, c->k, n, c->chk, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, c->chk, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "lbm_check_state");
+    const int64_t r[4] = {(int64_t)h[0], (int64_t)h[1], h[2] == ~0ull ? -1 : (int64_t)h[2],
+                          h[3] == ~0ull ? -1 : (int64_t)h[3]};
+    if (out4)
+        for (int j = 0; j < 4; ++j) out4[j] = r[j];
+    const int nx = c->p.nx;
+    char buf[256];
+    if (r[0] > 0) {
+        std::snprintf(buf, sizeof(buf), "non-finite state: %lld cells, first at x=%lld y=%lld",
+                      (long long)r[0], (long long)(r[2] % nx), (long long)(r[2] / nx));
+        set_error(buf);
+        return LBM_ENONFINITE;
+    }
+    if (r[1] > 0) {
+        std::snprintf(buf, sizeof(buf),
+                      "non-physical state (rho <= 0 or T <= 0): %lld cells, first at x=%lld y=%lld",
+                      (long long)r[1], (long long)(r[3] % nx), (long long)(r[3] / nx));
+        set_error(buf);
+        return LBM_ENONPHYS;
+    }
+    return LBM_OK;
 }
 
 int lbm_step_variant_count(void) { return step_variant_count(); }

@@ -159,6 +159,53 @@ __global__ void k_moments(const double* __restrict__ f, double* __restrict__ rho
     T[c] = E / r - 0.5 * (u * u + v * v);
 }
 
+// Counters of the state check: cells found non-finite and non-physical, and
+// the smallest index of each kind (all ones: none).
+__global__ void k_check_clear(unsigned long long* cnt)
+{
+    if (threadIdx.x < 4) cnt[threadIdx.x] = threadIdx.x < 2 ? 0ull : ~0ull;
+}
+
+// State check, one thread per cell: the moments of Eq. (10) must be finite
+// and have rho > 0, T > 0. Per wave, one atomic per counter: the number of
+// offending lanes and the first offending cell (lanes hold consecutive cells).
+__global__ __launch_bounds__(256) void k_check(const double* __restrict__ f, int64_t n, Consts k,
+                                               unsigned long long* cnt)
+{
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool bad = false, unphys = false;
+    if (c < n) {
+        double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
+        bool fin = true;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const double fi = f[i * n + c];
+            fin = fin && isfinite(fi);
+            r += fi;
+            jx = __builtin_fma(fi, k.vx[i], jx);
+            jy = __builtin_fma(fi, k.vy[i], jy);
+            E = __builtin_fma(fi, k.hv2[i], E);
+        }
+        const double ux = jx / r, uy = jy / r;
+        const double T = E / r - 0.5 * (ux * ux + uy * uy);
+        fin = fin && isfinite(r) && isfinite(ux) && isfinite(uy) && isfinite(T);
+        bad = !fin;
+        unphys = fin && !(r > 0.0 && T > 0.0);
+    }
+    const unsigned long long mb = __ballot(bad), mp = __ballot(unphys);
+    if ((threadIdx.x & 63) == 0) {
+        const unsigned long long w0 = (unsigned long long)(c);  // lane 0's cell
+        if (mb) {
+            atomicAdd(&cnt[0], (unsigned long long)__popcll(mb));
+            atomicMin(&cnt[2], w0 + (unsigned long long)(__ffsll((long long)mb) - 1));
+        }
+        if (mp) {
+            atomicAdd(&cnt[1], (unsigned long long)__popcll(mp));
+            atomicMin(&cnt[3], w0 + (unsigned long long)(__ffsll((long long)mp) - 1));
+        }
+    }
+}
+
 // Kinetic energy partials of rho u_n^2 / 2 (u_n = u_y, or u_x with ke_axis):
 // one (sum, max) pair per block of 256 cells.
 __global__ __launch_bounds__(256) void k_kinetic_part(const double* __restrict__ f, int64_t n,
@@ -346,6 +393,15 @@ hipError_t launch_moments(const double* f, double* rho, double* ux, double* uy, 
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_moments, dim3((unsigned)blocks), dim3(256), 0, st, f, rho, ux, uy, T, n,
                        k);
+    return hipGetLastError();
+}
+
+hipError_t launch_check(const double* f, const Consts& k, int64_t n, unsigned long long* cnt,
+                        hipStream_t st)
+{
+    hipLaunchKernelGGL(k_check_clear, dim3(1), dim3(64), 0, st, cnt);
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_check, dim3((unsigned)blocks), dim3(256), 0, st, f, n, k, cnt);
     return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ struct lbm_ctx {
     double* msum = nullptr;        // 2 x [4][ny][nx]: carried moment sums (ping-pong)
     double* gbuf = nullptr;        // outflow ghosts: [19][ny] per x side, [19][nx] per y side
     double* gb[4] = {nullptr, nullptr, nullptr, nullptr};  // per side into gbuf, or null
+    unsigned long long* chk = nullptr;  // 4 counters of lbm_check_state
 };
 
 int lbmi_validate(const lbm_params* p);
@@ -56,6 +57,8 @@ hipError_t launch_init(const double* rho, const double* ux, const double* uy, co
 hipError_t launch_side_eq(double* out, const double s[4][4], const Consts& k, hipStream_t st);
 hipError_t launch_moments(const double* f, double* rho, double* ux, double* uy, double* T,
                           const Consts& k, int64_t n, hipStream_t st);
+hipError_t launch_check(const double* f, const Consts& k, int64_t n, unsigned long long* cnt,
+                        hipStream_t st);
 hipError_t launch_kinetic_part(const double* f, const Consts& k, int64_t n, int ke_axis,
                                double* part, int* nparts, hipStream_t st);
 int adj_variant_count();

@@ -24,6 +24,7 @@ NV = 19
 PERIODIC, FIXED_EQ, REFLECT, OUTFLOW = 0, 1, 2, 3
 WENO5, UPWIND1, UPWIND2 = 0, 1, 2  # lbm_params.scheme
 LBM_OK, LBM_EINVAL, LBM_EUNSUPPORTED, LBM_EHIP, LBM_ENOMEM = 0, -1, -2, -3, -4
+LBM_ENONFINITE, LBM_ENONPHYS = -5, -6
 
 
 class LbmError(RuntimeError):
@@ -90,6 +91,7 @@ def lib():
         "lbm_step": (C.c_int, [_P, _P, _P, _I, _P, _P]),
         "lbm_moments": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
         "lbm_kinetic_y": (C.c_int, [_P, _P, _P, _P]),
+        "lbm_check_state": (C.c_int, [_P, _P, C.POINTER(C.c_int64), _P]),
         "lbm_step_variant_count": (C.c_int, []),
         "lbm_step_variant_info": (C.c_int, [_I, C.POINTER(_I)]),
         "lbm_set_step_variant": (C.c_int, [_P, _I]),
@@ -194,6 +196,17 @@ def lbm_moments(h, nx, ny, f, rho, ux, uy, T, stream=None):
 def lbm_kinetic_y(h, nx, ny, f, out2, stream=None):
     _check(lib().lbm_kinetic_y(h, _ptr(f, (NV, ny, nx), "f"), _ptr(out2, (2,), "out2"),
                                _stream(stream)))
+
+
+def lbm_check_state(h, nx, ny, f, stream=None, raise_error=True):
+    """(return code, (non-finite cells, non-physical cells, first non-finite
+    cell, first non-physical cell)); with raise_error a non-zero code raises
+    LbmError (whose .code is LBM_ENONFINITE or LBM_ENONPHYS)."""
+    out = (C.c_int64 * 4)()
+    rc = lib().lbm_check_state(h, _ptr(f, (NV, ny, nx), "f"), out, _stream(stream))
+    if raise_error:
+        _check(rc)
+    return rc, tuple(int(x) for x in out)
 
 
 def lbm_adjoint_step(h, nx, ny, f_n, lam_np1, w, lam_n, stream=None):
@@ -527,6 +540,10 @@ class Context:
         out = torch.empty(2, dtype=torch.float64, device=self.device)
         lbm_kinetic_y(self.handle, self.nx, self.ny, f, out)
         return out
+
+    def check(self, f, raise_error=True):
+        """lbm_check_state of f: (code, counts)."""
+        return lbm_check_state(self.handle, self.nx, self.ny, f, raise_error=raise_error)
 
     def adjoint_step(self, f_n, lam_np1, w=0.0, out=None):
         out = self.empty_f() if out is None else out
