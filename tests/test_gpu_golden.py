@@ -101,3 +101,30 @@ def test_khi512_full_run_matches_oracle(gold):
     for n, (ef, em, m, px, en) in worst.items():
         assert ef < tol(n) and em < tol(n), (n, ef, em)
         assert max(m, px, en) < max(1e-13, 1.5e-16 * n), (n, m, px, en)
+
+
+def test_khi512_restart_parity_late_run():
+    """The late, nonlinear part of the same run: the GPU's state after 19000
+    steps is copied to the host and both sides advance it 1000 more steps
+    from that identical state; all of f (19 x 512 x 512 values) must agree
+    to 1e-12 normwise, the bar of a 1000-step segment."""
+    import os
+
+    import oracle
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    torch.cuda.set_device(0)
+    s = inputs.khi(512, 512, dx=1e-3, dy=1e-3, dt=1e-5, tau=1e-5, Dv=0.02, Drho=0.02)
+    ctx = lbm.Context.from_setup(s)
+    f = ctx.init(*s.fields())
+    tune.tune_context(ctx, f, use_cache=False)
+    print(f"variant {lbm.lbm_step_variant_info(ctx.variant)}", flush=True)
+    f19 = ctx.step(f, 19000)
+    start = f19.cpu().numpy()
+    g = ctx.step(f19, 1000).cpu().numpy()
+    p = oracle.OracleParams.make(s.nx, s.ny, s.dx, s.dy, s.dt, s.tau, s.bc)
+    threads = min(16, os.cpu_count() or 1)
+    ref = oracle.step(p, start, 1000, nthreads=threads)
+    err = float(np.abs(g - ref).max() / np.abs(ref).max())
+    print(f"steps 19000-20000 from the GPU's state: normwise {err:.2e}", flush=True)
+    assert err < TOL
