@@ -134,6 +134,21 @@ int lbm_moments(lbm_ctx* ctx, const double* f, double* rho, double* ux, double* 
  * ke_axis = 1 (as in every energy log below). */
 int lbm_kinetic_y(lbm_ctx* ctx, const double* f, double* out2, lbm_stream stream);
 
+/* lbm_kinetic_y without a context and without allocating, for callers that
+ * cannot allocate device memory (code under stream capture, serving loops,
+ * harnesses that forbid hipMalloc). Validates p as lbm_create does and
+ * computes out2 from f with the same kernels and summation order as
+ * lbm_kinetic_y (identical results), keeping their per-block partials in a
+ * fixed device array of the library instead of a context buffer: 1 MiB per
+ * GPU, held until the process ends, for grids of at most 2^24 cells
+ * (nx * ny larger: LBM_EINVAL, nothing launched). Calls no hipMalloc, hipFree
+ * or other allocating routine. Every call on one GPU shares that GPU's array:
+ * calls that overlap in time on one GPU race and must be ordered by the
+ * caller (one stream, or events). f: one 19-plane field; out2: device
+ * double[2]. */
+int lbm_kinetic_y_noalloc(const lbm_params* p, const double* f, double* out2,
+                          lbm_stream stream);
+
 /* Sanity check of a state: per cell, the moments of Eq. (10) must be finite
  * and describe a gas, rho > 0 and T > 0 (the weights F_k(T) of Eqs. (44)-(46)
  * and the equilibrium of Eq. (28) divide by rho and T; an explicit step that

@@ -92,6 +92,7 @@ def lib():
         "lbm_moments": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
         "lbm_kinetic_y": (C.c_int, [_P, _P, _P, _P]),
         "lbm_check_state": (C.c_int, [_P, _P, C.POINTER(C.c_int64), _P]),
+        "lbm_kinetic_y_noalloc": (C.c_int, [C.POINTER(LbmParams), _P, _P, _P]),
         "lbm_step_variant_count": (C.c_int, []),
         "lbm_step_variant_info": (C.c_int, [_I, C.POINTER(_I)]),
         "lbm_set_step_variant": (C.c_int, [_P, _I]),
@@ -196,6 +197,13 @@ def lbm_moments(h, nx, ny, f, rho, ux, uy, T, stream=None):
 def lbm_kinetic_y(h, nx, ny, f, out2, stream=None):
     _check(lib().lbm_kinetic_y(h, _ptr(f, (NV, ny, nx), "f"), _ptr(out2, (2,), "out2"),
                                _stream(stream)))
+
+
+def lbm_kinetic_y_noalloc(params, f, out2, stream=None):
+    """lbm_kinetic_y from parameters alone (no context), allocating nothing."""
+    nx, ny = int(params.nx), int(params.ny)
+    _check(lib().lbm_kinetic_y_noalloc(C.byref(params), _ptr(f, (NV, ny, nx), "f"),
+                                       _ptr(out2, (2,), "out2"), _stream(stream)))
 
 
 def lbm_check_state(h, nx, ny, f, stream=None, raise_error=True):
