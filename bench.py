@@ -2,32 +2,35 @@
 
 A bench step is one forward-Euler time step (moments, equilibrium, WENO5
 convection of all 18 moving velocities along x and y, BGK relaxation,
-update) of the single shear-layer workload: 512 x 512 cells, periodic in x,
-reflecting walls in y, dx = dy = 1e-3, dt = tau = 1e-5, D_v = D_rho = 0.02,
-20000 steps. Inputs are seeded synthetic fields already resident in HBM when
-the timed region starts; the step variant is chosen by the autotuner before
-it.
+update) of the large shear-layer workload: 2048 x 2048 cells (about 640 MB per
+19-plane state), periodic in x, reflecting walls in y, dx = dy = 1e-3,
+dt = tau = 1e-5, D_v = 0.01, D_rho = 0.04. Its two states (1.28 GB) are far
+larger than the 256 MB Infinity Cache, so the step streams from HBM. Inputs
+are seeded synthetic fields already resident in HBM when the timed region
+starts; the step variant is chosen by the autotuner before it.
 
-Prints one JSON line. `value` is MLUPS (million lattice-site updates per
-second) of the timed run. `roofline` relates the step kernel's algorithmic
-HBM traffic (19 FP64 values read + 19 written = 304 B per site update) to the
-8 TB/s HBM3E peak, over the kernel's average launch duration: HIP events on
-the stream the kernel runs on bracket the timed region, which holds exactly
-`steps` launches of the step kernel and nothing else; `traffic` is the
-measured HBM traffic per launch from the committed rocprofv3 counter summary
-when it was taken on the current kernel sources. The timed run is repeated
-(--repeats, default 5 runs in all) and the spread goes to
-`extra.forward_512_repeats`; `value` is the first run. `extra` holds the other
-workloads: the 2048^2 forward step, the adjoint (reverse step alone and the
-full checkpointed gradient), the 64-instance batched sweep and the paper's
-transition-layer studies on its own shear layer. `cpu_baseline`
-is the CPU oracle timed on a bounded sample of the main workload.
+Prints one JSON line. The timed run (`steps` steps after `warmup` untimed
+ones) is repeated (--repeats, default 5 runs in all); `value` is the MLUPS
+(million lattice-site updates per second) of the median run and `ms_per_step`
+its time per step; every run is listed in `extra.forward_2048_repeats`.
+`roofline` relates the step's algorithmic HBM traffic (19 FP64 values read +
+19 written = 304 B per site update) to the 8 TB/s HBM3E peak over the median
+run's time per step: HIP events on the stream the kernels run on bracket each
+run, which holds exactly `steps` step launches (plus, for the carried-moment
+variants, one moment-sums pass over the input per call, amortised over the
+run). `traffic` is the measured HBM traffic per step from the committed
+rocprofv3 counter summary when it was taken on the current kernel sources.
+`extra` holds the other workloads: the 512 x 512 shear layer (whose two
+states fit the Infinity Cache), the adjoint (reverse step alone and the full
+checkpointed gradient), the 64-instance batched sweep and the paper's
+transition-layer studies on its own shear layer. `cpu_baseline` is the CPU
+oracle timed on a bounded sample of the main workload.
 
 Other modes (for the rocprofv3 runs whose summaries live in profiles/):
   --pmc-run        a few steps of the main workload plus a 512 MiB device
                    copy, for one counter pass
   --summarize ...  turn the kernel-trace and counter CSVs into the summary
-  --only PART      run one of the other workloads alone (forward2048, batch,
+  --only PART      run one of the other workloads alone (forward512, batch,
                    adjoint) and print its figures as one JSON line
   --trace-table D  per-kernel, per-grid-size durations of a rocprofv3
                    kernel trace under D, as a markdown table
@@ -54,8 +57,9 @@ BYTES_PER_LUP = 19 * 8 * 2          # forward: f^n read once, f^{n+1} written on
 ADJ_BYTES_PER_LUP = 19 * 8 * 3      # adjoint: f^n and lambda^{n+1} read, lambda^n written
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 512 << 20              # reference copy for the counter scale factors
-# counter summaries of the 512^2 step, one per profiled variant
-TRAFFIC_SUMMARIES = os.path.join(ROOT, "profiles", "k_step_*_khi512_counters.md")
+# counter summaries of the main workload's step, one per profiled variant
+TRAFFIC_SUMMARIES = os.path.join(ROOT, "profiles", "k_step_*_khi2048_counters.md")
+MAIN_N = 2048
 METRIC = "MLUPS (D2V19+WENO5, FP64) fwd/adjoint/batched + % HBM roofline"
 
 
@@ -84,6 +88,13 @@ def source_hash():
 
 
 def main_setup():
+    """The large shear layer: 2048^2, D_v = 0.01, D_rho = 0.04."""
+    from paper_1010_4124_amd import inputs
+    return inputs.khi(MAIN_N, MAIN_N, dx=1e-3, dy=1e-3, dt=1e-5, tau=1e-5, Dv=0.01, Drho=0.04)
+
+
+def small_setup():
+    """The single shear layer: 512^2, D_v = D_rho = 0.02."""
     from paper_1010_4124_amd import inputs
     return inputs.khi(512, 512, dx=1e-3, dy=1e-3, dt=1e-5, tau=1e-5, Dv=0.02, Drho=0.02)
 
@@ -128,56 +139,57 @@ def step_kernel_name(variant):
 
 
 # ---------------------------------------------------------------------------
-def bench_forward_main(args):
+def timed_forward(s, steps, warmup, repeats, variant=None, trial_steps=None, label=""):
+    """Tune (unless `variant` is given), warm up, then time `repeats` runs of
+    `steps` steps from the same initial state. Returns the context, the
+    per-run times and the median run's seconds and wall time."""
     import torch
     from paper_1010_4124_amd import lbm, tune
-    s = main_setup()
     ctx = lbm.Context.from_setup(s)
     f0 = ctx.init(*s.fields())
-    if args.variant is None:
-        t = tune.tune_context(ctx, f0, use_cache=False)
+    if variant is None:
+        kw = {"nsteps": trial_steps} if trial_steps else {}
+        t = tune.tune_context(ctx, f0, use_cache=False, **kw)
         how = f"tuned, ms/step {min(t['ms'].values()):.4f}"
     else:
-        ctx.variant = args.variant
+        ctx.variant = variant
         how = "fixed by --variant"
-    log(f"forward 512^2: variant {ctx.variant} {lbm.lbm_step_variant_info(ctx.variant)} ({how})")
+    log(f"{label}: variant {ctx.variant} {lbm.lbm_step_variant_info(ctx.variant)} ({how})")
     out = ctx.empty_f()
-    if args.warmup:
-        ctx.step(f0, args.warmup, out=out)
-    secs, wall = sync_time(lambda: ctx.step(f0, args.steps, out=out))
-    lups = s.nx * s.ny * args.steps
-    if not torch.isfinite(ctx.moments(out)[0]).all():
-        raise SystemExit("non-finite state after the timed run")
-    avg = secs / args.steps  # the timed region holds exactly these step launches
-    log(f"forward 512^2: {lups / secs / 1e6:.1f} MLUPS ({secs:.3f} s events, {wall:.3f} s wall), "
-        f"{avg * 1e6:.2f} us per launch")
-    # the same timed run repeated, for its spread (the reported value is the first)
-    runs = [secs] + [sync_time(lambda: ctx.step(f0, args.steps, out=out))[0]
-                     for _ in range(max(0, args.repeats - 1))]
-    ms = sorted(r / args.steps * 1e3 for r in runs)
-    rep = {"runs": len(runs), "ms_per_step": [r / args.steps * 1e3 for r in runs],
-           "median_ms_per_step": statistics.median(ms),
-           "median_MLUPS": s.nx * s.ny / statistics.median(ms) / 1e3}
-    log(f"forward 512^2 repeats: {rep}")
-    return s, ctx, f0, secs, wall, avg, rep
+    if warmup:
+        ctx.step(f0, warmup, out=out)
+    runs = [sync_time(lambda: ctx.step(f0, steps, out=out)) for _ in range(max(1, repeats))]
+    rc, counts = ctx.check(out, raise_error=False)
+    if rc != lbm.LBM_OK:
+        raise SystemExit(f"state check after the timed run failed: code {rc}, {counts}")
+    secs = [r[0] for r in runs]
+    med = statistics.median(secs)
+    k = secs.index(min(secs, key=lambda v: abs(v - med)))
+    rep = {"runs": len(secs), "ms_per_step": [v / steps * 1e3 for v in secs],
+           "median_ms_per_step": med / steps * 1e3,
+           "median_MLUPS": s.nx * s.ny * steps / med / 1e6,
+           "variant": list(lbm.lbm_step_variant_info(ctx.variant))}
+    log(f"{label}: {rep}")
+    return ctx, f0, rep, med, runs[k][1]
 
 
-def bench_forward_large(args):
-    from paper_1010_4124_amd import inputs, lbm, tune
-    big = inputs.khi(2048, 2048, dx=1e-3, dy=1e-3, dt=1e-5, tau=1e-5, Dv=0.01, Drho=0.04)
-    ctx = lbm.Context.from_setup(big)
-    f0 = ctx.init(*big.fields())
-    tune.tune_context(ctx, f0, nsteps=30, use_cache=False)
-    out = ctx.empty_f()
-    ctx.step(f0, 10, out=out)
-    secs, _ = sync_time(lambda: ctx.step(f0, args.large_steps, out=out))
-    lups = big.nx * big.ny * args.large_steps
-    r = {"MLUPS": lups / secs / 1e6, "steps": args.large_steps,
-         "variant": list(lbm.lbm_step_variant_info(ctx.variant)),
-         "us_per_step": secs / args.large_steps * 1e6,
-         "hbm_frac": BYTES_PER_LUP * lups / secs / 1e9 / HBM_PEAK_GBS}
-    log(f"forward 2048^2: {r}")
-    return r
+def bench_forward_main(args):
+    s = main_setup()
+    ctx, f0, rep, secs, wall = timed_forward(s, args.steps, args.warmup, args.repeats,
+                                             args.variant, trial_steps=30,
+                                             label=f"forward {s.nx}^2")
+    return s, ctx, f0, secs, wall, secs / args.steps, rep
+
+
+def bench_forward_small(args):
+    s = small_setup()
+    ctx, f0, rep, secs, _ = timed_forward(s, args.small_steps, 200, args.repeats,
+                                          label=f"forward {s.nx}^2")
+    rep["steps"] = args.small_steps
+    rep["hbm_frac"] = BYTES_PER_LUP * s.nx * s.ny * args.small_steps / secs / 1e9 / HBM_PEAK_GBS
+    rep["kernel"] = step_kernel_name(ctx.variant)
+    del ctx, f0
+    return rep
 
 
 def _variants(ctx):
@@ -276,11 +288,13 @@ def bench_batch(args):
     lbm.lbm_batch_step(b.handle, f0, out, 100, ke[:, :100].contiguous())  # warm: capture graph
     secs, _ = sync_time(lambda: lbm.lbm_batch_step(b.handle, f0, out, args.batch_steps, ke))
     kel = ke.cpu().numpy()
+    # growth rates over the linear stage each log shows within the configured
+    # run (t <= 0.1, so 0.05-long stages); instances still in the initial
+    # transient have no straight rising stage (r2 < 0.99) and are not counted
     gam, below = [], 0
     for i, (d, s) in enumerate(zip(draw, setups)):
-        try:
-            g, _ = growth.growth_rate(kel[i], s.dt)
-        except ValueError:
+        g, r2, _ = growth.linear_stage(kel[i], s.dt, width=0.05)
+        if not r2 >= 0.99:
             continue
         gam.append(g)
         below += g < growth.classical_rate(d["nx"] * s.dx)
@@ -288,7 +302,8 @@ def bench_batch(args):
          "MLUPS": b.cells * args.batch_steps / secs / 1e6,
          "variant": list(lbm.lbm_step_variant_info(b.variant)), "slots_per_xcd": b.schedule[0],
          "graph_chunk": b.schedule[1], "ke_logged": True,
-         "gamma": {"fitted": len(gam), "median": float(np.median(gam)) if gam else None,
+         "gamma": {"fit": "linear stage of the domain-integral log, 0.05 long, r2 >= 0.99",
+                   "fitted": len(gam), "median": float(np.median(gam)) if gam else None,
                    "min": float(np.min(gam)) if gam else None,
                    "max": float(np.max(gam)) if gam else None, "below_classical": int(below)}}
     log(f"batched sweep: {r}")
@@ -309,6 +324,9 @@ def bench_paper_studies():
 
 
 def cpu_baseline(setup, seconds):
+    """The oracle as it stands on the GPU run's host: the first steps of the
+    main workload from its initial state, on up to 16 threads (OpenMP over
+    rows) and on one thread, each within a time budget."""
     import oracle
     p = oracle.OracleParams.make(setup.nx, setup.ny, setup.dx, setup.dy, setup.dt, setup.tau,
                                  setup.bc)
@@ -316,7 +334,7 @@ def cpu_baseline(setup, seconds):
     threads = min(16, os.cpu_count() or 1)
 
     def timed(nthreads, budget):
-        f, steps, chunk = f0, 0, 10 if nthreads > 1 else 1
+        f, steps, chunk = f0, 0, 1
         t0 = time.perf_counter()
         while time.perf_counter() - t0 < budget and steps < 5000:
             f = oracle.step(p, f, chunk, nthreads=nthreads)
@@ -334,8 +352,9 @@ def cpu_baseline(setup, seconds):
         pass
     return {"value": setup.nx * setup.ny * steps / dt / 1e6, "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
-            "sample": f"{setup.nx}x{setup.ny} shear layer (the main workload), first {steps} "
-                      f"of its steps from the same initial state, {dt:.1f} s on {threads} threads",
+            "sample": f"{setup.nx}x{setup.ny} shear layer (the main workload), its first "
+                      f"{steps} steps from the same initial state, {dt:.1f} s on {threads} "
+                      "threads (a rate measured on this sample, not a full-length run)",
             "single_thread_MLUPS": setup.nx * setup.ny * steps1 / dt1 / 1e6,
             "single_thread_sample": f"first {steps1} steps, {dt1:.1f} s on 1 thread",
             "host_cpus": os.cpu_count(), "cpu_model": model}
@@ -542,7 +561,7 @@ def _pmc_main(args):
     ctx = lbm.Context.from_setup(s)
     f0 = ctx.init(*s.fields())
     if args.variant is None:
-        tune.tune_context(ctx, f0, use_cache=False)
+        tune.tune_context(ctx, f0, nsteps=30, use_cache=False)
     else:
         ctx.variant = args.variant
     log(f"pmc run: variant {ctx.variant} {lbm.lbm_step_variant_info(ctx.variant)}")
@@ -603,10 +622,10 @@ def summarize(args):
     w_k, w_c = per_dispatch(write, "WRITE_SIZE")
     sf, sw = COPY_BYTES / (f_c * 1024.0), COPY_BYTES / (w_c * 1024.0)
     traffic = f_k * 1024.0 * sf + w_k * 1024.0 * sw
-    cells = 512 * 512
+    cells = MAIN_N * MAIN_N
     algo = BYTES_PER_LUP * cells
     lines = [
-        "# Step kernel(s), 512 x 512 shear layer: duration and HBM traffic per step",
+        f"# Step kernel(s), {MAIN_N} x {MAIN_N} shear layer: duration and HBM traffic per step",
         "",
         f"kernel: {name}",
         f"source_sha1: {source_hash()}",
@@ -635,13 +654,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--repeats", type=int, default=5,
-                    help="timed runs of the main workload; the first is the reported value")
+                    help="timed runs of the main workload; the median is the reported value")
     ap.add_argument("--variant", type=int, default=None,
                     help="step variant of the main workload (default: autotuned)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--large-steps", type=int, default=200)
+    ap.add_argument("--small-steps", type=int, default=2000,
+                    help="timed steps per run of the 512^2 shear layer in extra")
     ap.add_argument("--adj-steps", type=int, default=4000)
     ap.add_argument("--adj-large-steps", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=10000)
@@ -650,7 +670,7 @@ def main():
     ap.add_argument("--pmc-run", action="store_true")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE", "FETCH", "WRITE"))
     ap.add_argument("--commands", nargs="*")
-    ap.add_argument("--only", choices=("forward2048", "batch", "adjoint"))
+    ap.add_argument("--only", choices=("forward512", "batch", "adjoint"))
     ap.add_argument("--trace-table", metavar="TRACE")
     ap.add_argument("--counter-table", metavar="PMC")
     ap.add_argument("--match", nargs="*", default=[])
@@ -684,7 +704,7 @@ def main():
         pmc_run(args)
         return
     if args.only:
-        part = {"forward2048": bench_forward_large, "batch": bench_batch,
+        part = {"forward512": bench_forward_small, "batch": bench_batch,
                 "adjoint": bench_adjoint}[args.only]
         print(json.dumps({args.only: part(args)}), flush=True)
         return
@@ -699,9 +719,10 @@ def main():
     del ctx, f0
     torch.cuda.empty_cache()
 
-    extra = {"forward_512_repeats": rep}
+    extra = {"forward_2048_repeats": rep}
     if not args.no_extra:
-        extra["forward_2048"] = bench_forward_large(args)
+        extra["forward_512"] = bench_forward_small(args)
+        torch.cuda.empty_cache()
         extra["batched_sweep"] = bench_batch(args)
         extra["paper_studies"] = bench_paper_studies()
         extra["adjoint"] = bench_adjoint(args)
@@ -719,9 +740,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "single shear layer (KHI) 512x512, periodic x, reflecting walls "
-                               "in y, dx=dy=1e-3, dt=tau=1e-5, D_v=D_rho=0.02, forward step",
-                   "nx": 512, "ny": 512, "steps": args.steps, "wall_s": wall},
+        "config": {"workload": f"large shear layer (KHI) {s.nx}x{s.ny}, periodic x, reflecting "
+                               "walls in y, dx=dy=1e-3, dt=tau=1e-5, D_v=0.01, D_rho=0.04, "
+                               "forward step (median of the timed runs)",
+                   "nx": s.nx, "ny": s.ny, "steps": args.steps, "repeats": rep["runs"],
+                   "wall_s": wall},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kname, "avg_launch_us": avg * 1e6,
