@@ -45,6 +45,34 @@ def growth_rate(ke, dt, window=(0.02, 0.1), column=1):
     return 0.5 * float(coef[0]), r2
 
 
+def linear_stage(ke, dt, width=0.1, tmin=0.02, step=0.01, column=0):
+    """Growth rate over the linear growth stage, found in the log itself.
+
+    Sec. IV fits the slope of ln E to "the initial growth stage", after the
+    initial transient and before saturation, in each run separately. Here
+    that stage is the window [a, a + width] (a >= tmin, on a grid of `step`)
+    in which ln E rises and is closest to a straight line: of the windows
+    with a positive slope, the one whose least-squares fit has the largest
+    coefficient of determination r2. Column 0 (the domain integral of
+    rho u_n^2 / 2) is the default: with walls in y, sound waves trapped
+    between them make the peak (column 1) jump from place to place, while
+    both grow like exp(2 gamma t) in the linear stage.
+
+    Returns (gamma, r2, a), or (nan, 0.0, nan) when no window rises.
+    """
+    ke = np.asarray(ke, dtype=np.float64)
+    t_end = (ke.shape[0] - 1) * float(dt)
+    best = (math.nan, 0.0, math.nan)
+    for a in np.arange(tmin, t_end - width + 0.5 * step, step):
+        try:
+            g, r2 = growth_rate(ke, dt, window=(a, a + width), column=column)
+        except ValueError:
+            continue
+        if g > 0.0 and r2 > best[1]:
+            best = (g, r2, float(a))
+    return best
+
+
 def classical_rate(Lx, rho1=5.0, rho2=2.0, dv=1.0, mode=1):
     """gamma_c = k sqrt(rho1 rho2) dv / (rho1 + rho2), k = 2 pi mode / Lx."""
     k = 2.0 * math.pi * mode / Lx

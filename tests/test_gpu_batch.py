@@ -224,25 +224,53 @@ def test_sweep_full_size_two_steps_vs_oracle():
 
 
 def test_sweep_growth_rates_below_classical():
-    """10000 steps of the sweep with graph replays and per-instance energy
-    logs: mass is conserved per instance, and every fitted linear growth rate
-    stays below the sharp-interface rate k sqrt(rho1 rho2) dv/(rho1 + rho2)."""
+    """The configured 10000-step sweep (t = 0.1) ends inside the initial
+    transient for most instances, so this validation run of the same 64
+    instances lasts 40000 steps (t = 0.4), with graph replays and
+    per-instance energy logs. Per instance: mass is conserved, and the
+    growth rate is fitted over the linear growth stage found in its own log
+    (growth.linear_stage, the Sec. IV fit). Asserted:
+      - thin velocity layers in the smaller boxes (k D_v <= 0.4, L_x <= 0.192,
+        where growth outruns the sound waves trapped between the walls within
+        the run) grow: gamma > 0 with r2 >= 0.99;
+      - every rate measured on a straight stage (r2 >= 0.99) stays below the
+        sharp-interface rate k sqrt(rho1 rho2) dv / (rho1 + rho2) (Sec. IV.A);
+      - gamma / gamma_c falls as k D_v grows (Sec. IV.A: wider velocity
+        layers grow more slowly), rank correlation <= -0.8 over the straight
+        stages of the boxes with L_x <= 0.192.
+    The density-layer trend of Sec. IV.B is checked on the paper's own
+    controlled study (test_gpu_paper_trends): here D_v and D_rho are drawn
+    together and most D_rho lie beyond the effective width below which the
+    paper finds that trend."""
+    from scipy.stats import spearmanr
     draw, setups = shear_batch(2024)
     b, scal = make_batch(setups)
     f0 = b.init(*scal)
     b.schedule = (0, 100)
-    nsteps = 10000
+    nsteps = 40000
     f1, ke = b.step(f0, nsteps, ke_log=True)
     m0 = b.moments(f0)[0]
     m1 = b.moments(f1)[0]
     ke = ke.cpu().numpy()
+    rows = []
     for i, (d, s) in enumerate(zip(draw, setups)):
         M0 = float(b.scalar_view(m0, i).sum())
         M1 = float(b.scalar_view(m1, i).sum())
         assert abs(M1 - M0) <= 1e-12 * M0
         assert np.isfinite(ke[i]).all()
-        g, r2 = growth.growth_rate(ke[i], s.dt)
-        gc = growth.classical_rate(d["nx"] * s.dx)
-        print(f"{i:2d} {d['nx']}x{d['ny']} Dv={d['Dv']:.4f} Drho={d['Drho']:.4f}: "
-              f"gamma={g:.3f} (r2 {r2:.3f}) gamma_c={gc:.2f}", flush=True)
-        assert g < gc
+        g, r2, a = growth.linear_stage(ke[i], s.dt)
+        Lx = d["nx"] * s.dx
+        gc = growth.classical_rate(Lx)
+        kDv = 2 * np.pi / Lx * d["Dv"]
+        rows.append((g, r2, gc, kDv, Lx))
+        print(f"{i:2d} {d['nx']}x{d['ny']} Dv={d['Dv']:.4f} Drho={d['Drho']:.4f} kDv={kDv:.2f}: "
+              f"gamma={g:.3f} (r2 {r2:.4f}, stage from t={a:.2f}) gamma_c={gc:.2f}", flush=True)
+        if kDv <= 0.4 and Lx <= 0.192 + 1e-12:
+            assert g > 0 and r2 >= 0.99, i
+        if r2 >= 0.99:
+            assert g < gc, i
+    sel = [(g / gc, kDv) for g, r2, gc, kDv, Lx in rows if r2 >= 0.99 and Lx <= 0.192 + 1e-12]
+    rho = spearmanr([q[0] for q in sel], [q[1] for q in sel])[0]
+    print(f"{len(sel)} straight stages in boxes L_x <= 0.192: rank correlation of "
+          f"gamma/gamma_c with k D_v {rho:.3f}", flush=True)
+    assert len(sel) >= 10 and rho <= -0.8

@@ -56,3 +56,26 @@ def test_classical_rate():
     assert abs(growth.classical_rate(0.128) - 22.18) < 5e-3
     # symmetric in the densities, linear in the shear jump and the mode
     assert growth.classical_rate(1.0, 2, 5, 2.0, 3) == pytest.approx(6 * growth.classical_rate(1.0))
+
+
+def test_linear_stage_found_between_transient_and_saturation():
+    """A decaying, oscillating transient, then exponential growth at
+    gamma = 6 from t = 0.12 to 0.3, then saturation: the stage search lands
+    inside the growth and returns gamma."""
+    dt = 1e-4
+    t = np.arange(4001) * dt
+    lnE = np.where(t < 0.12, -10.0 - 20.0 * t + 0.5 * np.sin(200 * t), 0.0)
+    grow = -12.4 + 2 * 6.0 * (t - 0.12)
+    lnE = np.where((t >= 0.12) & (t <= 0.3), grow, lnE)
+    lnE = np.where(t > 0.3, -12.4 + 2 * 6.0 * 0.18, lnE)
+    E = np.exp(lnE)
+    g, r2, a = growth.linear_stage(np.stack([E, E], 1), dt, width=0.1)
+    assert abs(g - 6.0) < 1e-9 and r2 > 1 - 1e-12 and 0.12 - 1e-9 <= a <= 0.2 + 1e-9
+
+
+def test_linear_stage_reports_no_growth():
+    dt = 1e-4
+    t = np.arange(3001) * dt
+    E = np.exp(-3.0 * t)
+    g, r2, a = growth.linear_stage(np.stack([E, E], 1), dt)
+    assert math.isnan(g) and r2 == 0.0 and math.isnan(a)
