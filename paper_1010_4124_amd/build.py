@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import glob
 import os
+import re
 import subprocess
 import sys
 import tempfile
@@ -34,7 +35,24 @@ def _run(cmd, verbose):
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-    return r.returncode
+    return r.returncode, r.stderr
+
+
+def scratch_kernels(remarks):
+    """Kernels whose per-lane scratch (private segment) is not zero, from the
+    compiler's kernel resource-usage remarks: [(name, bytes per lane)]."""
+    out, name = [], None
+    for ln in remarks.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", ln)
+        if m:
+            name = m.group(1)
+            continue
+        m = re.search(r"remark:\s+ScratchSize \[bytes/lane\]: (\d+)", ln)
+        if m and name is not None:
+            if int(m.group(1)) > 0:
+                out.append((name, int(m.group(1))))
+            name = None
+    return out
 
 
 def build(verbose: bool = False) -> str:
@@ -53,6 +71,7 @@ def build(verbose: bool = False) -> str:
              "-mllvm", "-instcombine-max-copied-from-constant-users=100000",
              "-Wall", "-Wno-unused-result",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Rpass-analysis=kernel-resource-usage",
              "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
     with tempfile.TemporaryDirectory(prefix="lbm_build_") as tmpd:
         objs, cmds = [], []
@@ -62,11 +81,18 @@ def build(verbose: bool = False) -> str:
             cmds.append([hipcc, *flags, "-c", src, "-o", obj])
         jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
         with ThreadPoolExecutor(jobs) as ex:
-            codes = list(ex.map(lambda c: _run(c, verbose), cmds))
-        if any(codes):
+            res = list(ex.map(lambda c: _run(c, verbose), cmds))
+        if any(rc for rc, _ in res):
             raise RuntimeError("hipcc failed compiling liblbm_hip sources")
+        # No kernel may spill to scratch memory: builds of step variants that
+        # spilled gave wrong results once, for a reason not found, so every
+        # variant offered must fit its register budget.
+        spills = [k for _, err in res for k in scratch_kernels(err)]
+        if spills:
+            raise RuntimeError(f"kernels with scratch (register spills): {spills}")
         tmp = LIB + ".tmp%d" % os.getpid()
-        if _run([hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp], verbose):
+        if _run([hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp],
+                verbose)[0]:
             raise RuntimeError("hipcc failed linking liblbm_hip.so")
     os.replace(tmp, LIB)
     return LIB

@@ -695,9 +695,10 @@ struct AdjVariant {
 };
 
 #define LBM_ADJ_VARIANT(R, G, W, PS) {R, G, W, PS, k_adjoint<R, G, W, PS>},
-// (multi-plane groups under the two-wave budget spill and are left out)
+// (no variant may spill registers: multi-plane groups under the two-wave
+// budget, and one velocity group per tile, are left out for that)
 static const AdjVariant kAdjVariants[] = {
-    LBM_ADJ_VARIANT(4, 1, 1, 0) LBM_ADJ_VARIANT(4, 3, 1, 0) LBM_ADJ_VARIANT(4, 6, 1, 0)
+    LBM_ADJ_VARIANT(4, 3, 1, 0) LBM_ADJ_VARIANT(4, 6, 1, 0)
     LBM_ADJ_VARIANT(4, 18, 1, 1) LBM_ADJ_VARIANT(4, 18, 2, 1) LBM_ADJ_VARIANT(2, 18, 2, 1)
     LBM_ADJ_VARIANT(4, 6, 1, 1) LBM_ADJ_VARIANT(4, 3, 1, 1)
 };

@@ -174,11 +174,9 @@ struct BatchVariant {
     int R, G, M;
     void (*kernel)(BatchArgs);
 };
-// The batched kernel keeps an instance descriptor live as well: where the
-// single-grid variant targets four or more waves per SIMD it gets one wave
-// less, so that no instantiation has to spill.
-#define LBM_BATCH_VARIANT(R, G, W, D, NT, M) \
-    {R, G, M, k_step_batch<R, G, ((W) >= 4 ? (W) - 1 : (W)), D, NT, M>},
+// The batched kernel keeps an instance descriptor live as well and takes the
+// variant's own batch wave target WB, chosen so that it does not spill.
+#define LBM_BATCH_VARIANT(R, G, W, D, NT, M, WB) {R, G, M, k_step_batch<R, G, WB, D, NT, M>},
 static const BatchVariant kBatchVariants[] = {LBM_STEP_VARIANTS(LBM_BATCH_VARIANT)};
 #undef LBM_BATCH_VARIANT
 

@@ -274,7 +274,7 @@ struct StepVariant {
     void (*kernel)(StepArgs);
 };
 
-#define LBM_SINGLE_VARIANT(R, G, W, D, NT, M) {R, G, W, D, NT, M, k_step<R, G, W, D, NT, M>},
+#define LBM_SINGLE_VARIANT(R, G, W, D, NT, M, WB) {R, G, W, D, NT, M, k_step<R, G, W, D, NT, M>},
 static const StepVariant kStepVariants[] = {LBM_STEP_VARIANTS(LBM_SINGLE_VARIANT)};
 #undef LBM_SINGLE_VARIANT
 constexpr int kNumStepVariants = sizeof(kStepVariants) / sizeof(kStepVariants[0]);

@@ -604,20 +604,21 @@ __device__ __forceinline__ void step_work(const StepGrid& a, const Consts& k, SE
 
 // Step kernel variants: rows per lane R, velocity groups G (18/G moving
 // velocities each), the wavefronts-per-SIMD target W that bounds the register
-// budget, planes in flight D, non-temporal stores NT and the phase-1 mode M
+// budget, planes in flight D, non-temporal stores NT, the phase-1 mode M
 // (PH_SUMS, PH_CARRY: the G groups are the waves of one workgroup, PH_STATE:
-// a state pass runs first). Both the
+// a state pass runs first) and the wave target WB of the batched kernel,
+// which keeps an instance descriptor live as well and so may need a larger
+// register budget (a lower target) for the same variant. Both the
 // single-grid and the batched kernel are instantiated for every entry, in
-// this order. Variants that the 128-register budget of W = 4 forces to spill
-// are left out: two such builds gave wrong results on a 5 x 3 grid with
-// fixed x sides.
+// this order. No kernel may spill registers to scratch memory (the build
+// refuses one that does): the targets are chosen so that none does.
 #define LBM_STEP_VARIANTS(X)                                                                     \
-    X(4, 1, 3, 1, 0, 0) X(4, 3, 3, 1, 0, 0) X(8, 2, 2, 1, 0, 0) X(8, 1, 2, 1, 0, 0)               \
-    X(2, 3, 4, 1, 0, 0) X(4, 1, 3, 2, 0, 0) X(4, 3, 3, 2, 0, 0) X(8, 1, 2, 2, 0, 0)               \
-    X(8, 2, 2, 1, 1, 0) X(4, 1, 3, 2, 1, 0) X(4, 2, 3, 1, 0, 0) X(4, 3, 3, 1, 0, 1)               \
-    X(4, 2, 3, 1, 0, 1) X(4, 1, 2, 1, 0, 1) X(4, 1, 2, 2, 1, 1) X(4, 3, 2, 1, 1, 1)               \
-    X(4, 1, 2, 2, 0, 1) X(4, 18, 4, 1, 0, 2) X(2, 18, 5, 1, 0, 2) X(8, 18, 3, 1, 0, 2)            \
-    X(4, 3, 3, 1, 0, 2) X(2, 9, 4, 1, 0, 2) X(2, 6, 4, 1, 0, 2) X(4, 9, 3, 1, 0, 2)               \
-    X(4, 6, 3, 1, 0, 2)
+    X(4, 1, 3, 1, 0, 0, 2) X(4, 3, 3, 1, 0, 0, 2) X(8, 2, 2, 1, 0, 0, 1)                         \
+    X(8, 1, 2, 1, 0, 0, 1) X(2, 3, 4, 1, 0, 0, 3) X(8, 2, 2, 1, 1, 0, 1)                         \
+    X(4, 2, 3, 1, 0, 0, 2) X(4, 1, 2, 1, 0, 1, 2) X(4, 1, 2, 2, 1, 1, 2)                         \
+    X(4, 3, 2, 1, 1, 1, 2) X(4, 1, 2, 2, 0, 1, 2) X(4, 18, 4, 1, 0, 2, 3)                        \
+    X(2, 18, 5, 1, 0, 2, 4) X(4, 3, 3, 1, 0, 2, 3)                                               \
+    X(2, 9, 4, 1, 0, 2, 3) X(2, 6, 4, 1, 0, 2, 3) X(4, 9, 3, 1, 0, 2, 3)                         \
+    X(4, 6, 3, 1, 0, 2, 3) X(2, 1, 3, 1, 1, 1, 3) X(2, 1, 3, 1, 0, 1, 3)
 
 }  // namespace lbmd
