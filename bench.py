@@ -70,7 +70,7 @@ def log(msg):
 # what the profiled step kernels (k_step, k_state) are compiled from: their
 # translation unit, the headers it includes and the build script's flags
 STEP_SOURCES = [os.path.join(ROOT, "paper_1010_4124_amd", "csrc", f) for f in
-                ("lbm_forward.hip", "lbm_device.h", "lbm_internal.h", "lbm_stage.h",
+                ("lbm_forward.hip", "lbm_device.h", "lbm_fast.h", "lbm_internal.h", "lbm_stage.h",
                  "lbm_step.h")] + [os.path.join(ROOT, "include", "lbm.h"),
                                    os.path.join(ROOT, "paper_1010_4124_amd", "build.py")]
 
@@ -150,7 +150,9 @@ def timed_forward(s, steps, warmup, repeats, variant=None, trial_steps=None, lab
     if variant is None:
         kw = {"nsteps": trial_steps} if trial_steps else {}
         t = tune.tune_context(ctx, f0, use_cache=False, **kw)
-        how = f"tuned, ms/step {min(t['ms'].values()):.4f}"
+        top = sorted(t["ms"].items(), key=lambda q: q[1])[:4]
+        how = "tuned; fastest ms/step " + ", ".join(
+            f"{lbm.lbm_step_variant_info(int(v))}: {ms:.4f}" for v, ms in top)
     else:
         ctx.variant = variant
         how = "fixed by --variant"

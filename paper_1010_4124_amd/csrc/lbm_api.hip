@@ -264,7 +264,8 @@ int lbm_step(lbm_ctx* c, const double* f_in, double* f_out, int32_t nsteps, doub
     int info[6];
     step_variant_desc(c->variant, info);
     const int mode = info[5];
-    if (mode == 1) {
+    const bool carry = mode == 1 || mode == 3;  // carried moment sums
+    if (carry) {
         // moment sums of f_in; each step then reads one set and writes the other
         hipError_t e = launch_sums(f_in, c->msum, c->k, n, st);
         if (e != hipSuccess) return hip_fail(e, "lbm_step sums");
@@ -282,7 +283,7 @@ int lbm_step(lbm_ctx* c, const double* f_in, double* f_out, int32_t nsteps, doub
             hipError_t e = launch_outflow(src, p.nx, p.ny, c->gb, c->k, st);
             if (e != hipSuccess) return hip_fail(e, "lbm_step outflow");
         }
-        if (mode == 1) {
+        if (carry) {
             m_in = c->msum + 4 * n * (s % 2);
             m_out = c->msum + 4 * n * ((s + 1) % 2);
         } else if (mode == 2) {
@@ -384,14 +385,14 @@ int lbm_get_step_variant(lbm_ctx* c, int32_t* v)
 
 // Default step variant (the autotuner can override it per context or batch),
 // the fastest measured on MI355X: on small grids a state pass and one
-// velocity per workgroup; on large grids (or batches) carried moment sums,
-// two planes in flight and non-temporal stores.
+// velocity per workgroup; on large grids (or batches) carried moment sums
+// with the fast-tile kernel and non-temporal stores.
 int lbmi_default_variant(int nx, int ny) { return lbmi_default_variant_cells((int64_t)nx * ny); }
 
 int lbmi_default_variant_cells(int64_t cells)
 {
     const bool large = cells >= (1ll << 21);
-    const int small_v[6] = {4, 18, 4, 1, 0, 2}, large_v[6] = {4, 1, 2, 2, 1, 1};
+    const int small_v[6] = {4, 18, 4, 1, 0, 2}, large_v[6] = {4, 1, 2, 1, 1, 3};
     const int* want = large ? large_v : small_v;
     for (int v = 0; v < step_variant_count(); ++v) {
         int d[6];

@@ -175,8 +175,12 @@ struct BatchVariant {
     void (*kernel)(BatchArgs);
 };
 // The batched kernel keeps an instance descriptor live as well and takes the
-// variant's own batch wave target WB, chosen so that it does not spill.
-#define LBM_BATCH_VARIANT(R, G, W, D, NT, M, WB) {R, G, M, k_step_batch<R, G, WB, D, NT, M>},
+// variant's own batch wave target WB, chosen so that it does not spill. The
+// fast-tile variants (M = 3) run their PH_CARRY form here: on every tile they
+// compute what the fast kernel computes, bit for bit.
+#define LBM_BATCH_VARIANT(R, G, W, D, NT, M, WB)                                          \
+    {R, G, (M == PH_FAST ? PH_CARRY : M),                                                 \
+     k_step_batch<R, G, WB, D, NT, (M == PH_FAST ? PH_CARRY : M)>},
 static const BatchVariant kBatchVariants[] = {LBM_STEP_VARIANTS(LBM_BATCH_VARIANT)};
 #undef LBM_BATCH_VARIANT
 

@@ -13,6 +13,7 @@
 // The remaining kernels here are the cell-parallel helpers: f^eq
 // initialisation, side equilibria, moments and the kinetic-energy reduction.
 #include "lbm_device.h"
+#include "lbm_fast.h"
 #include "lbm_internal.h"
 #include "lbm_stage.h"
 #include "lbm_step.h"
@@ -26,6 +27,8 @@ struct StepArgs {
     double* __restrict__ m_out;
     int tiles_y;
     int nwork, per_xcd;  // work items: tiles (M = 1) or tiles x groups (M = 0, 2)
+    int nband;           // M = 3: work items [0, nband) are the tiles around `rect`
+    FastRect rect;       // M = 3: the rectangle of fast tiles
     Consts k;
 };
 
@@ -44,6 +47,39 @@ void k_step(StepArgs a)
     step_work<R, G, DEPTH, NT, MODE>(a.s, a.k, SideEqConsts{}, tile, grp,
                                    a.ke_part ? a.ke_part + 2 * tile : nullptr, lds, a.m_in,
                                    a.m_out);
+}
+
+// The M = 3 variants (lbm_fast.h): the first nband work items are the tiles
+// around the rectangle of fast tiles, advanced by the PH_CARRY tile body
+// (dispatched first, so that their longer path overlaps the rest); the
+// others walk the rectangle in strips with the fast-tile body. XCD-major as
+// in k_step. One launch covers the grid.
+template <int R, int W, int DEPTH, bool NT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_step_fast(StepArgs a)
+{
+    constexpr int NL = FastStage<R>::LDS > WaveLds<R, PH_CARRY>::SIZE ? FastStage<R>::LDS
+                                                                     : WaveLds<R, PH_CARRY>::SIZE;
+    __shared__ double lds[NL];
+
+    const int b = blockIdx.x;
+    const int work = (b & 7) * a.per_xcd + (b >> 3);
+    if (work >= a.nwork) return;
+    const FastRect& f = a.rect;
+    if (work < a.nband) {
+        const int tile = band_tile(work, f, a.s.tiles_x, a.tiles_y);
+        step_work<R, 1, DEPTH, NT, PH_CARRY>(a.s, a.k, SideEqConsts{}, tile, 0,
+                                             a.ke_part ? a.ke_part + 2 * tile : nullptr, lds,
+                                             a.m_in, a.m_out);
+        return;
+    }
+    const int cols = f.c1 - f.c0, rows = f.r1 - f.r0;
+    const int t = strip_walk(work - a.nband, cols, rows);
+    const int ty = t / cols, tx = t - ty * cols;
+    const int tile = (f.r0 + ty) * a.s.tiles_x + f.c0 + tx;
+    // the host's rectangle holds fast tiles only; never stage another here
+    if (!fast_tile(grid_bc(a.s), (f.c0 + tx) * TX, (f.r0 + ty) * R, TX, R, HALO)) return;
+    fast_tile_work<R, DEPTH, NT>(a.s, a.k, tile, a.ke_part ? a.ke_part + 2 * tile : nullptr, lds,
+                                 a.m_in, a.m_out);
 }
 
 // State pass of the PH_STATE variants, one thread per cell (state_block).
@@ -274,7 +310,18 @@ struct StepVariant {
     void (*kernel)(StepArgs);
 };
 
-#define LBM_SINGLE_VARIANT(R, G, W, D, NT, M, WB) {R, G, W, D, NT, M, k_step<R, G, W, D, NT, M>},
+template <int R, int G, int W, int D, bool NT, int M>
+struct StepKernel {
+    static constexpr void (*fn)(StepArgs) = k_step<R, G, W, D, NT, M>;
+};
+template <int R, int G, int W, int D, bool NT>
+struct StepKernel<R, G, W, D, NT, PH_FAST> {
+    static_assert(G == 1, "the fast-tile kernel advances all 18 velocities in one wave");
+    static constexpr void (*fn)(StepArgs) = k_step_fast<R, W, D, NT>;
+};
+
+#define LBM_SINGLE_VARIANT(R, G, W, D, NT, M, WB) \
+    {R, G, W, D, NT, M, StepKernel<R, G, W, D, NT, M>::fn},
 static const StepVariant kStepVariants[] = {LBM_STEP_VARIANTS(LBM_SINGLE_VARIANT)};
 #undef LBM_SINGLE_VARIANT
 constexpr int kNumStepVariants = sizeof(kStepVariants) / sizeof(kStepVariants[0]);
@@ -323,9 +370,21 @@ hipError_t launch_step(int variant, const double* fin, double* fout, const Const
     a.m_in = m_in;
     a.m_out = m_out;
     a.tiles_y = (ny + V.R - 1) / V.R;
+    a.k = k;
+    a.nband = 0;
+    a.rect = FastRect{0, 0, a.tiles_y, a.tiles_y};
+    if (V.M == PH_FAST) {
+        // the tiles around the rectangle of fast tiles first, then the
+        // rectangle: every tile once
+        a.rect = fast_rect(nx, ny, bc[XLO], V.R);
+        a.nband = band_count(a.rect, a.s.tiles_x, a.tiles_y);
+        a.nwork = a.nband + (a.rect.c1 - a.rect.c0) * (a.rect.r1 - a.rect.r0);
+        a.per_xcd = (a.nwork + 7) / 8;
+        hipLaunchKernelGGL(V.kernel, dim3(8 * a.per_xcd), dim3(64), 0, st, a);
+        return hipGetLastError();
+    }
     a.nwork = a.s.tiles_x * a.tiles_y * (V.M == PH_CARRY ? 1 : V.G);
     a.per_xcd = (a.nwork + 7) / 8;
-    a.k = k;
     hipLaunchKernelGGL(V.kernel, dim3(8 * a.per_xcd), dim3(64 * (V.M == PH_CARRY ? V.G : 1)), 0,
                        st, a);
     return hipGetLastError();

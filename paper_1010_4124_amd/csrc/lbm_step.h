@@ -225,6 +225,7 @@ enum {
     PH_SUMS = 0,   // sum the 19 planes of f^n
     PH_CARRY = 1,  // read the sums rho, j, E the previous step wrote
     PH_STATE = 2,  // read the cell state (dt/tau rho, T, u/T, v/T) a state pass wrote
+    PH_FAST = 3,   // carried sums as PH_CARRY; fast tiles by the kernel of lbm_fast.h
 };
 
 // Waves per workgroup of a variant: the G groups are waves of one workgroup
@@ -606,7 +607,9 @@ __device__ __forceinline__ void step_work(const StepGrid& a, const Consts& k, SE
 // velocities each), the wavefronts-per-SIMD target W that bounds the register
 // budget, planes in flight D, non-temporal stores NT, the phase-1 mode M
 // (PH_SUMS, PH_CARRY: the G groups are the waves of one workgroup, PH_STATE:
-// a state pass runs first) and the wave target WB of the batched kernel,
+// a state pass runs first, PH_FAST: PH_CARRY with the fast tiles advanced by
+// the kernel of lbm_fast.h and the others by the PH_CARRY kernel) and the
+// wave target WB of the batched kernel,
 // which keeps an instance descriptor live as well and so may need a larger
 // register budget (a lower target) for the same variant. Both the
 // single-grid and the batched kernel are instantiated for every entry, in
@@ -619,6 +622,7 @@ __device__ __forceinline__ void step_work(const StepGrid& a, const Consts& k, SE
     X(4, 3, 2, 1, 1, 1, 2) X(4, 1, 2, 2, 0, 1, 2) X(4, 18, 4, 1, 0, 2, 3)                        \
     X(2, 18, 5, 1, 0, 2, 4) X(4, 3, 3, 1, 0, 2, 3)                                               \
     X(2, 9, 4, 1, 0, 2, 3) X(2, 6, 4, 1, 0, 2, 3) X(4, 9, 3, 1, 0, 2, 3)                         \
-    X(4, 6, 3, 1, 0, 2, 3) X(2, 1, 3, 1, 1, 1, 3) X(2, 1, 3, 1, 0, 1, 3)
+    X(4, 6, 3, 1, 0, 2, 3) X(2, 1, 3, 1, 1, 1, 3) X(2, 1, 3, 1, 0, 1, 3)                         \
+    X(4, 1, 2, 1, 1, 3, 2) X(4, 1, 2, 2, 1, 3, 2) X(4, 1, 2, 1, 0, 3, 2)
 
 }  // namespace lbmd

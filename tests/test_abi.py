@@ -27,7 +27,7 @@ def test_version_and_variants_without_gpu():
     for v in range(n):
         R, G, W, D, NT, M = lbm.lbm_step_variant_info(v)
         assert R in (1, 2, 4, 8) and G in (1, 2, 3, 6, 9, 18) and W >= 1 and D in (1, 2)
-        assert NT in (0, 1) and M in (0, 1, 2) and 18 % G == 0
+        assert NT in (0, 1) and M in (0, 1, 2, 3) and 18 % G == 0
     with pytest.raises(lbm.LbmError):
         lbm.lbm_step_variant_info(n)
     na = lbm.lbm_adjoint_variant_count()
