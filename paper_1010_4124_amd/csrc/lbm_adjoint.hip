@@ -59,8 +59,9 @@ __device__ __forceinline__ GridBC grid_of(const AdjArgs& a)
 
 __device__ __forceinline__ double dweight_c(const Consts& k, int s, double T)
 {
-    // dF_k/dT of T (Fc + T (Fb + T Fa))
-    return __builtin_fma(T, __builtin_fma(3.0 * T, k.Fa[s], 2.0 * k.Fb[s]), k.Fc[s]);
+    // dF_k/dT: (72 T^2 - 8 (b + c) T + b c) / den, the derivative of weight_c's
+    // closed form
+    return __builtin_fma(T, __builtin_fma(T, 72.0, -2.0 * k.Fc4[s]), k.Fbc[s]) * k.Frden[s];
 }
 
 // Reverse mode of one WENO5 face given its shared differences (the same

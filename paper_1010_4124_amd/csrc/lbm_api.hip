@@ -82,7 +82,7 @@ int lbmi_validate(const lbm_params* p)
 }
 
 // Host image of the per-context constants: velocity components from the
-// exact direction tables, |v|^2/2, the folded weight polynomials of
+// exact direction tables, |v|^2/2, the coefficients of the weights of
 // Eqs. (44)-(46) and the mirror partners.
 void lbmi_fill_consts(const lbm_params* p, Consts* h)
 {
@@ -103,9 +103,10 @@ void lbmi_fill_consts(const lbm_params* p, Consts* h)
         const double b = p->vk[(k + 1) % 3] * p->vk[(k + 1) % 3];
         const double c = p->vk[(k + 2) % 3] * p->vk[(k + 2) % 3];
         const double den = 3.0 * a * (a - b) * (a - c);
-        h->Fa[k] = 24.0 / den;
-        h->Fb[k] = -4.0 * (b + c) / den;
-        h->Fc[k] = b * c / den;
+        h->Fc4[k] = 4.0 * (b + c);
+        h->Fbc[k] = b * c;
+        h->Fden[k] = den;
+        h->Frden[k] = 1.0 / den;
     }
     h->eps = p->weno_eps;
     for (int i = 0; i < NV; ++i) {

@@ -35,9 +35,11 @@ __host__ __device__ constexpr int mirror_x_dir(int d) { return (7 - d) % 6; }
 struct Consts {
     double vx[NV], vy[NV];  // v_i components
     double hv2[NV];         // |v_i|^2 / 2
-    // F_k(T) = T (Fc + T (Fb + T Fa)) for k = 1..3: the closed form of
-    // Eqs. (44)-(46) with the constant denominator folded in.
-    double Fa[3], Fb[3], Fc[3];
+    // F_k(T) = T (T (24 T - Fc4) + Fbc) / Fden for k = 1..3, the closed form
+    // of Eqs. (44)-(46): Fc4 = 4 (b + c), Fbc = b c, Fden = 3 a (a - b) (a - c)
+    // with a, b, c the squared speeds of shells k, k+1, k+2 (cyclic), and
+    // Frden = 1 / Fden rounded to nearest.
+    double Fc4[3], Fbc[3], Fden[3], Frden[3];
     double eps;             // WENO regulariser of Eq. (52)
     double epsx[NV], epsy[NV];  // eps / v_ix^2 and eps / v_iy^2 (0 where v = 0):
                                 // the regulariser of WENO on f (weno_faces)
@@ -45,10 +47,19 @@ struct Consts {
     int mirx[NV], miry[NV]; // indices of (-vx, vy) and (vx, -vy)
 };
 
-// F_k(T) of speed shell s = k-1 (Eqs. (44)-(46)).
+// F_k(T) of speed shell s = k-1 (Eqs. (44)-(46)): the numerator in Horner
+// form with its own coefficients (24, 4(b+c), bc), then the quotient by the
+// denominator as P r corrected once by its residual, (P - den q) r, with r
+// the rounded reciprocal. The coefficients are not divided by the
+// denominator first: each would then carry a fixed rounding error, the same
+// in every cell and step, which F_0 = 1 - 6 (F_1 + F_2 + F_3) amplifies and
+// which a long run accumulates linearly (here ~2e-16 of f per step); the
+// errors of this form vary in sign from cell to cell and step to step.
 __device__ __forceinline__ double weight_c(const Consts& k, int s, double T)
 {
-    return T * __builtin_fma(T, __builtin_fma(T, k.Fa[s], k.Fb[s]), k.Fc[s]);
+    const double P = T * __builtin_fma(T, __builtin_fma(T, 24.0, -k.Fc4[s]), k.Fbc[s]);
+    const double q = P * k.Frden[s];
+    return __builtin_fma(__builtin_fma(-k.Fden[s], q, P), k.Frden[s], q);
 }
 
 // Per-cell quantities the equilibrium needs, from the raw sums of Eq. (10):
