@@ -1,19 +1,22 @@
 """The single shear-layer workload at full size and full length (512 x 512,
-20000 steps, the launch configuration the benchmark times) against the
-oracle's stored run (tests/golden/khi512_oracle.npz, written by
-tests/golden/make_khi512_golden.py from oracle/ alone).
+20000 steps, periodic x, walls in y) against the oracle's stored run
+(tests/golden/khi512_oracle.npz, written by tests/golden/make_khi512_golden.py
+from oracle/ alone).
 
 Compared: f at 4096 seeded samples and the moments at 1024 seeded cells
 after 1000, 5000 and 20000 steps (normwise against max |f|), the energy log
-every 100 steps, and the conserved totals.
+every 100 steps, and the conserved totals; and, from the GPU's state after
+19000 steps, all of f after 1000 more steps on both sides.
 
-Tolerance. Both sides evaluate the same formulas in a different order (the
-oracle: f^eq with divisions, unfused sums, the BGK term as written; the
-kernel: division-free regrouped WENO weights and equilibrium, fused
-multiply-adds, (1 - dt/tau) f + (dt/tau) f^eq). One step differs by a few
-units in the last place of f, about 3e-16 max|f|, and the difference is
-carried forward. The bar is the 1e-12 normwise parity up to 1000 steps and
-DRIFT * n beyond (DRIFT = 3.5e-16 per step, above the measured 2-3e-16)."""
+Tolerance. f and the moments: 1e-12 normwise at every checkpoint. Both sides
+evaluate the same formulas in a different order, and a long run carries the
+difference forward; how far legal roundings of Eq. (47) drift apart on this
+flow is recorded in tests/golden/khi512_drift.json (the oracle built with
+and without fused multiply-adds: 3.3e-13 of f after 20000 steps, saturating).
+The energy log E_y: relative to E_y itself, at most 3 times what those two
+oracle builds differ by over the run (E_y is ~1e-7 of the flow's kinetic
+energy, a small difference of O(1) sums, so its relative error is the drift
+of f amplified), and against the kinetic energy scale at 1e-12."""
 import os
 
 import numpy as np
@@ -24,12 +27,18 @@ from paper_1010_4124_amd import inputs, lbm, tune
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "khi512_oracle.npz")
+DRIFT_EVIDENCE = os.path.join(os.path.dirname(__file__), "golden", "khi512_drift.json")
 TOL = 1e-12
-DRIFT = 3.5e-16
+EY_FACTOR = 3.0
 
 
-def tol(n):
-    return max(TOL, DRIFT * n)
+def ey_bars():
+    """Relative E_y bars (sum, max columns): EY_FACTOR times the largest
+    difference between the two oracle builds over the 20000-step run."""
+    import json
+    rows = json.load(open(DRIFT_EVIDENCE))["rows"]
+    return (EY_FACTOR * max(r["ke_sum_rel"] for r in rows),
+            EY_FACTOR * max(r["ke_max_rel"] for r in rows))
 
 
 @pytest.fixture(scope="module")
@@ -91,16 +100,17 @@ def test_khi512_full_run_matches_oracle(gold):
     # error against the flow's kinetic energy sum rho |u|^2 / 2 dx dy
     r0, ux0, uy0, _ = s.fields()
     e_kin = float((0.5 * r0 * (ux0 ** 2 + uy0 ** 2)).sum()) * s.dx * s.dy
-    steps = np.arange(got.shape[0]) * every
+    bars = ey_bars()
     for c, scale in ((0, e_kin), (1, float((0.5 * r0 * (ux0 ** 2 + uy0 ** 2)).max()))):
         d = np.abs(got[:, c] - ref[:, c]) / scale
         rel = np.abs(got[:, c] - ref[:, c]) / np.abs(ref[:, c])
         print(f"energy log column {c}: worst error {d.max():.2e} of the kinetic energy scale, "
-              f"{rel.max():.2e} relative to E_y itself", flush=True)
-        assert np.all(d <= np.maximum(TOL, DRIFT * steps)), c
+              f"{rel.max():.2e} relative to E_y itself (bar {bars[c]:.2e})", flush=True)
+        assert d.max() <= TOL, c
+        assert rel.max() <= bars[c], c
     for n, (ef, em, m, px, en) in worst.items():
-        assert ef < tol(n) and em < tol(n), (n, ef, em)
-        assert max(m, px, en) < max(1e-13, 1.5e-16 * n), (n, m, px, en)
+        assert ef < TOL and em < TOL, (n, ef, em)
+        assert max(m, px, en) < 1e-13, (n, m, px, en)
 
 
 def test_khi512_restart_parity_late_run():
