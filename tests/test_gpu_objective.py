@@ -1,9 +1,10 @@
 """Gradient of the shear-layer objective J = dt sum_{n0..n1} E_y(f^n) with
 respect to the layer widths D_v, D_rho and the perturbation mode amplitudes:
 the GPU adjoint with checkpoint/recompute (a) against a CPU pipeline built
-only from the oracle (forward, reverse sweep, init VJP), and (b) at the full
+only from the oracle (forward, reverse sweep, init VJP), (b) at the full
 256 x 256, 4000-step workload against central finite differences (h = 1e-6)
-to a relative error of 1e-5."""
+to a relative error of 1e-5, and (c) at that full size against the CPU
+reverse-mode oracle's stored gradient to 1e-8 relative, element by element."""
 import numpy as np
 import pytest
 import torch
@@ -97,6 +98,35 @@ def test_full_size_gradient_vs_central_fd():
     assert gDv == pytest.approx(fd_dv, rel=1e-5)
     assert gDrho == pytest.approx(fd_dr, rel=1e-5)
     assert np.dot(ga, d) == pytest.approx(fd_a, rel=1e-5)
+
+
+def test_full_size_gradient_vs_cpu_reverse_mode():
+    """The same 256 x 256, 4000-step gradient against the CPU reverse-mode
+    oracle at full size (tests/golden/khi256_gradient.npz, written by
+    tests/golden/make_khi256_gradient.py from oracle/ alone: the oracle's
+    forward and adjoint steps with checkpoints every 200 steps, its init VJP
+    and the input recipe's tangents). J, dJ/dD_v, dJ/dD_rho and each of the
+    256 mode amplitudes' derivatives to 1e-8 relative."""
+    import os
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "khi256_gradient.npz"))
+    n, nsteps, n0, n1, seed = (int(v) for v in gold["setup"])
+    Dv, Drho = (float(v) for v in gold["widths"])
+    amps = inputs.mode_amplitudes(n, seed=seed)
+    assert np.array_equal(amps, gold["amps"])
+    prob = KHIProblem(n, n, nsteps=nsteps, window=(n0, n1), schedule=Schedule.every(200))
+    J, ck = prob.run(Dv, Drho, amps)
+    gDv, gDrho, ga = prob.gradient(Dv, Drho, amps, ck)
+    del ck
+    rel = lambda a, b: abs(a - b) / abs(b)  # noqa: E731
+    ea = np.abs(ga - gold["da"]) / np.abs(gold["da"])
+    print(f"J {rel(J, float(gold['J'])):.2e}, dJ/dDv {rel(gDv, float(gold['dDv'])):.2e}, "
+          f"dJ/dDrho {rel(gDrho, float(gold['dDrho'])):.2e}, amplitudes: worst {ea.max():.2e} "
+          f"(|dJ/da| from {np.abs(gold['da']).min():.2e} to {np.abs(gold['da']).max():.2e})",
+          flush=True)
+    assert rel(J, float(gold["J"])) < 1e-8
+    assert rel(gDv, float(gold["dDv"])) < 1e-8
+    assert rel(gDrho, float(gold["dDrho"])) < 1e-8
+    assert ea.max() < 1e-8
 
 
 @pytest.mark.parametrize("nsteps,sch", [(60, Schedule(30, 6)), (70, Schedule(30, 6)),
