@@ -26,6 +26,7 @@
 
 #include "lbm.h"
 #include "lbm_device.h"
+#include "lbm_fast.h"
 #include "lbm_internal.h"
 #include "lbm_stage.h"
 #include "lbm_step.h"
@@ -67,7 +68,12 @@ template <int R, int G, int W, int DEPTH, bool NT, int MODE>
 __global__ __launch_bounds__((64 * Waves<G, MODE>::N)) __attribute__((amdgpu_waves_per_eu(W)))
 void k_step_batch(BatchArgs a)
 {
-    __shared__ double lds[Waves<G, MODE>::N * WaveLds<R, MODE>::SIZE];
+    // PH_FAST: fast tiles take the fast-tile body (lbm_fast.h), the others
+    // the PH_CARRY body, tile by tile as the single-grid launch divides them
+    constexpr int ML = MODE == PH_FAST ? PH_CARRY : MODE;
+    constexpr int NL0 = Waves<G, ML>::N * WaveLds<R, ML>::SIZE;
+    constexpr int NL = MODE == PH_FAST && FastStage<R>::LDS > NL0 ? FastStage<R>::LDS : NL0;
+    __shared__ double lds[NL];
 
     const int b = blockIdx.x;
     const int lo = (b & 7) * a.per_xcd;
@@ -91,13 +97,21 @@ void k_step_batch(BatchArgs a)
         s.cx = d.cx;
         s.cy = d.cy;
         s.ct = d.ct;
-        constexpr int GW = MODE == PH_CARRY ? 1 : G;
+        constexpr int GW = ML == PH_CARRY ? 1 : G;
         const int tile = it.y / GW, grp = it.y - tile * GW;
-        step_work<R, G, DEPTH, NT, MODE>(
-            s, a.k, SideEqPtr{d.side_eq}, tile, grp,
-            a.ke_part ? a.ke_part + 2 * ((int64_t)d.ke_off + tile) : nullptr, lds,
-            MODE != PH_SUMS ? a.m_in + d.moff : nullptr,
-            MODE == PH_CARRY ? a.m_out + d.moff : nullptr);
+        double* ke = a.ke_part ? a.ke_part + 2 * ((int64_t)d.ke_off + tile) : nullptr;
+        if constexpr (MODE == PH_FAST) {
+            const int ty = tile / s.tiles_x, tx = tile - ty * s.tiles_x;
+            if (fast_tile(grid_bc(s), tx * TX, ty * R, TX, R, HALO)) {
+                fast_tile_work<R, DEPTH, NT>(s, a.k, tile, ke, lds, a.m_in + d.moff,
+                                             a.m_out + d.moff);
+                __syncthreads();  // LDS is reused by the next item
+                continue;
+            }
+        }
+        step_work<R, G, DEPTH, NT, ML>(s, a.k, SideEqPtr{d.side_eq}, tile, grp, ke, lds,
+                                       ML != PH_SUMS ? a.m_in + d.moff : nullptr,
+                                       ML == PH_CARRY ? a.m_out + d.moff : nullptr);
         __syncthreads();  // LDS is reused by the next item
     }
 }
@@ -176,11 +190,10 @@ struct BatchVariant {
 };
 // The batched kernel keeps an instance descriptor live as well and takes the
 // variant's own batch wave target WB, chosen so that it does not spill. The
-// fast-tile variants (M = 3) run their PH_CARRY form here: on every tile they
-// compute what the fast kernel computes, bit for bit.
-#define LBM_BATCH_VARIANT(R, G, W, D, NT, M, WB)                                          \
-    {R, G, (M == PH_FAST ? PH_CARRY : M),                                                 \
-     k_step_batch<R, G, WB, D, NT, (M == PH_FAST ? PH_CARRY : M)>},
+// host side treats the fast-tile variants (M = 3) as carried-moment ones:
+// same work items, sums and buffers.
+#define LBM_BATCH_VARIANT(R, G, W, D, NT, M, WB) \
+    {R, G, (M == PH_FAST ? PH_CARRY : M), k_step_batch<R, G, WB, D, NT, M>},
 static const BatchVariant kBatchVariants[] = {LBM_STEP_VARIANTS(LBM_BATCH_VARIANT)};
 #undef LBM_BATCH_VARIANT
 
