@@ -131,11 +131,19 @@ def read_traffic(kernel_name, pattern=None):
 
 def step_kernel_name(variant):
     """The step's kernel(s): a state-pass variant (M = 2) launches k_state and
-    then the step kernel each step; both count as the step."""
+    then the step kernel each step; both count as the step. The fast-tile
+    variants (M = 3) launch k_step_fast<R, W, D, NT>."""
     from paper_1010_4124_amd import lbm
     R, G, W, D, NT, M = lbm.lbm_step_variant_info(variant)
-    name = f"lbmd::k_step<{R}, {G}, {W}, {D}, {'true' if NT else 'false'}, {M}>"
+    nt = "true" if NT else "false"
+    if M == 3:
+        return f"lbmd::k_step_fast<{R}, {W}, {D}, {nt}>"
+    name = f"lbmd::k_step<{R}, {G}, {W}, {D}, {nt}, {M}>"
     return name + " + lbmd::k_state" if M == 2 else name
+
+
+def _is_step(name):
+    return "k_step<" in name or "k_step_fast<" in name
 
 
 # ---------------------------------------------------------------------------
@@ -214,6 +222,7 @@ def tune_problem(prob):
 
 
 def bench_adjoint(args):
+    import numpy as np
     import torch
     from paper_1010_4124_amd import inputs, lbm, objective, tune
     res = {}
@@ -258,11 +267,18 @@ def bench_adjoint(args):
     tune_problem(prob2)
     amps2 = inputs.mode_amplitudes(2048, seed=7)
     fsecs, _ = sync_time(lambda: prob2.run(0.01, 0.04, amps2, keep_checkpoints=False))
+    torch.cuda.reset_peak_memory_stats()
     J2, ck2 = prob2.run(0.01, 0.04, amps2)
-    gsecs, _ = sync_time(lambda: prob2.gradient(0.01, 0.04, amps2, ck=ck2))
+    grad2 = []
+    gsecs, _ = sync_time(lambda: grad2.append(prob2.gradient(0.01, 0.04, amps2, ck=ck2)))
+    gDv2, gDrho2, ga2 = grad2[0]
     l2 = 2048 * 2048 * n2
     res["gradient_2048"] = {"steps": n2, "schedule": [prob2.schedule.K1, prob2.schedule.K2],
                             "forward_MLUPS": l2 / fsecs / 1e6, "adjoint_MLUPS": l2 / gsecs / 1e6,
+                            "peak_device_GB": torch.cuda.max_memory_allocated() / 1e9,
+                            "finite": bool(np.isfinite([J2, gDv2, gDrho2]).all()
+                                           and np.isfinite(ga2).all()),
+                            "J": J2, "dJ_dDv": gDv2, "dJ_dDrho": gDrho2,
                             "variants": _variants(prob2.ctx)}
     log(f"adjoint: {res}")
     del prob, prob2, ck, ck2
@@ -567,7 +583,10 @@ def _pmc_main(args):
     else:
         ctx.variant = args.variant
     log(f"pmc run: variant {ctx.variant} {lbm.lbm_step_variant_info(ctx.variant)}")
-    ctx.step(f0, args.steps, out=ctx.empty_f())
+    out = ctx.empty_f()
+    if args.warmup:
+        ctx.step(f0, args.warmup, out=out)  # as in the benchmark: a warm GPU
+    ctx.step(f0, args.steps, out=out)
 
 
 def _rows(pattern):
@@ -579,37 +598,57 @@ def _rows(pattern):
     return rows
 
 
+def _kname(r, key="Kernel_Name"):
+    return re.sub(r"^void ", "", r[key]).split("(")[0]
+
+
+def _last(rows, n):
+    """The last n rows in dispatch order (the timed call of a --pmc-run)."""
+    rows = sorted(rows, key=lambda r: int(r.get("Dispatch_Id", r.get("Correlation_Id", 0))))
+    return rows[-n:]
+
+
 def summarize(args):
-    """Markdown summary of the kernel-trace stats and the two counter passes."""
+    """Markdown summary of the kernel trace and the two counter passes of a
+    --pmc-run: durations and counters of the step kernel(s) over the last
+    --last dispatches (the timed call; the warm-up call comes first)."""
     trace, fetch, write = args.summarize
+    n_last = args.last
     stats = _rows(os.path.join(trace, "**", "*kernel_stats.csv"))
-    step = [r for r in stats if "k_step<" in r["Name"]]
+    kt = _rows(os.path.join(trace, "**", "*kernel_trace.csv"))
+    step = [r for r in stats if _is_step(r["Name"])]
     if not step:
         raise SystemExit(f"no step kernel in {trace}")
     # the tuner launches every variant a few times; the timed one dominates
     top = max(step, key=lambda r: int(r["Calls"]))
     base = re.sub(r"^void ", "", top["Name"]).split("(")[0]
-    avg_ns = float(top["AverageNs"])
+
+    def durations(kernel):
+        rows = _last([r for r in kt if _kname(r) == kernel], n_last)
+        return [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows]
+
+    dur = durations(base)
     parts = [base]
     if base.endswith(", 2>"):
-        st = [r for r in stats if r["Name"].startswith("lbmd::k_state(")]
-        if not st:
+        sd = durations("lbmd::k_state")
+        if not sd:
             raise SystemExit("state-pass variant without k_state in the trace")
-        avg_ns += float(st[0]["AverageNs"])
+        dur = [a + b for a, b in zip(dur, sd)]
         parts.append("lbmd::k_state")
+    avg_ns = statistics.mean(dur)
     name = " + ".join(parts)
 
     def per_dispatch(root, counter):
         rows = _rows(os.path.join(root, "**", "*counter_collection.csv"))
         by = {}
         for r in rows:
-            if ("k_step<" in r["Kernel_Name"] or r["Kernel_Name"].startswith("lbmd::k_state(")) \
+            if (_is_step(r["Kernel_Name"]) or r["Kernel_Name"].startswith("lbmd::k_state(")) \
                     and r["Counter_Name"] == counter:
-                k = re.sub(r"^void ", "", r["Kernel_Name"]).split("(")[0]
-                by.setdefault(k, []).append(float(r["Counter_Value"]))
+                by.setdefault(_kname(r), []).append(r)
+        by = {k: [float(r["Counter_Value"]) for r in _last(v, n_last)] for k, v in by.items()}
         cp = [(int(r["Grid_Size"]), float(r["Counter_Value"])) for r in rows
               if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == counter]
-        steps = {k: v for k, v in by.items() if "k_step<" in k}
+        steps = {k: v for k, v in by.items() if _is_step(k)}
         if not steps or not cp:
             raise SystemExit(f"{counter}: step or copy dispatches missing in {root}")
         k = max(steps, key=lambda q: len(steps[q]))
@@ -620,6 +659,7 @@ def summarize(args):
             total += statistics.mean(by["lbmd::k_state"])
         return total, max(cp)[1]
 
+    sums = [r for r in stats if r["Name"].startswith("lbmd::k_sums(")]
     f_k, f_c = per_dispatch(fetch, "FETCH_SIZE")
     w_k, w_c = per_dispatch(write, "WRITE_SIZE")
     sf, sw = COPY_BYTES / (f_c * 1024.0), COPY_BYTES / (w_c * 1024.0)
@@ -631,8 +671,10 @@ def summarize(args):
         "",
         f"kernel: {name}",
         f"source_sha1: {source_hash()}",
-        f"avg_duration_ns: {avg_ns:.1f} (per step, all of its kernels)",
-        f"calls: {top['Calls']}",
+        f"avg_duration_ns: {avg_ns:.1f} (per step, all of its kernels, mean of the last "
+        f"{len(dur)} dispatches: the timed call)",
+        f"median_duration_ns: {statistics.median(dur):.1f}",
+        f"calls: {top['Calls']} (warm-up and timed calls)",
         f"fetch_kib_per_dispatch: {f_k:.1f}",
         f"write_kib_per_dispatch: {w_k:.1f}",
         f"copy_fetch_kib: {f_c:.1f} (512 MiB copy; scale {sf:.4f})",
@@ -642,9 +684,29 @@ def summarize(args):
         f"traffic_per_lup: {traffic / cells:.1f} B (algorithmic 304 B)",
         f"achieved_algorithmic_GBs: {algo / avg_ns:.1f}",
         f"achieved_measured_GBs: {traffic / avg_ns:.1f}",
-        "",
-        "Commands (repository root, TMPDIR=/tmp):",
     ]
+    if sums:
+        lines.append(f"moment_sums_pass_ns: {float(sums[0]['AverageNs']):.1f} (k_sums, once per "
+                     f"lbm_step call of a carried-moment variant; {sums[0]['Calls']} calls)")
+    for d in args.sq or []:
+        rows = _rows(os.path.join(d, "**", "*counter_collection.csv"))
+        byc = {}
+        for r in rows:
+            if _kname(r) == base:
+                byc.setdefault(r["Counter_Name"], []).append(r)
+        by = {c: [float(r["Counter_Value"]) for r in _last(v, n_last)] for c, v in byc.items()}
+        if not by:
+            raise SystemExit(f"no {base} dispatches in {d}")
+        lines += ["", f"SQ counters ({d.rstrip('/').split('/')[-1]}), mean per dispatch of {base}:", ""]
+        lines += [f"    {c}: {statistics.mean(v):.1f}" for c, v in sorted(by.items())]
+        if "SQ_INSTS_VALU" in by and "SQ_WAVES" in by:
+            valu = statistics.mean(by["SQ_INSTS_VALU"])
+            lines.append(f"    VALU instructions per wave: {valu / statistics.mean(by['SQ_WAVES']):.0f}; "
+                         f"per site update (64 lanes): {valu * 64 / cells:.0f}")
+            lines.append(f"    VALU issue share (4 cycles per wave64 instruction, 1024 SIMDs, "
+                         f"2.4 GHz, over the traced duration): "
+                         f"{valu * 4 / 1024 / (avg_ns * 2.4):.2f}")
+    lines += ["", "Commands (repository root, TMPDIR=/tmp):"]
     lines += ["    " + c for c in args.commands] if args.commands else []
     print("\n".join(lines))
 
@@ -672,6 +734,9 @@ def main():
     ap.add_argument("--pmc-run", action="store_true")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE", "FETCH", "WRITE"))
     ap.add_argument("--commands", nargs="*")
+    ap.add_argument("--sq", nargs="*", help="SQ counter-pass directories for --summarize")
+    ap.add_argument("--last", type=int, default=20,
+                    help="--summarize: dispatches of the timed call (its last ones)")
     ap.add_argument("--only", choices=("forward512", "batch", "adjoint"))
     ap.add_argument("--trace-table", metavar="TRACE")
     ap.add_argument("--counter-table", metavar="PMC")
