@@ -180,7 +180,10 @@ int lbm_adjoint_step(lbm_ctx* ctx, const double* f_n, const double* lam_np1, dou
  * PS): tiles of 64 x R cells, the 18 moving velocities split into G groups
  * (one workgroup per tile and group), W the wavefronts-per-SIMD target, and
  * PS = 1 when a per-cell pass first forms the equilibrium/objective terms
- * and the rest plane (then the context's [4][ny][nx] buffer holds them).
+ * and the rest plane (then the context's [4][ny][nx] buffer holds them);
+ * PS = 2: the same pass, then one workgroup per moving velocity marches
+ * along y over 64-column strips in chunks of R rows, each face evaluated
+ * once, the tiles next to non-periodic sides as PS = 1 with R = 4.
  * Every variant computes the same result up to rounding. */
 int lbm_adjoint_variant_count(void);
 int lbm_adjoint_variant_info(int32_t variant, int32_t* info4);

@@ -29,6 +29,7 @@
 // values of its mirror j, so cells within three cells of the wall also gather
 // the wall faces of plane j.
 #include "lbm_device.h"
+#include "lbm_fast.h"
 #include "lbm_internal.h"
 #include "lbm_stage.h"
 
@@ -48,6 +49,8 @@ struct AdjArgs {
     int bc[4];
     int tiles_x, tiles_y, nwork, per_xcd;
     double cx, cy, ct, wdxdy;  // w dx dy: weight of the objective term
+    FastRect rect;             // marching variants: the marched tiles (64 x 4 units)
+    int mh, nstrip, nchunk;    // marching variants: chunk rows, strips, chunks
     Consts k;
 };
 
@@ -520,8 +523,9 @@ __device__ __forceinline__ AdjCell adj_cell(FV&& fv, LV&& lv, const Consts& k, d
 }
 
 // One (tile, group) work item of the reverse step. PS: the K's come from
-// a.kst (written with the rest plane by k_adj_state).
-template <int R, int G, int W, bool PS>
+// a.kst (written with the rest plane by k_adj_state). BAND: the tiles are
+// those around a.rect (band_tile), the rest being marched by k_adj_march.
+template <int R, int G, int W, bool PS, bool BAND = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_adjoint(AdjArgs a)
 {
     using SF = StageG<R, FH, AP>;
@@ -536,7 +540,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_
     if (work >= a.nwork) return;
     const int tile = work / G, grp = work - tile * G;
     const int lane = threadIdx.x;
-    const int rm = strip_walk(tile, a.tiles_x, a.tiles_y);
+    const int rm = BAND ? band_tile(tile, a.rect, a.tiles_x, a.tiles_y)
+                        : strip_walk(tile, a.tiles_x, a.tiles_y);
     const int ty = rm / a.tiles_x, tx = rm - ty * a.tiles_x;
     const int x0 = tx * ATX, y0 = ty * R;
     const int64_t plane = (int64_t)a.nx * a.ny;
@@ -610,6 +615,390 @@ __global__ __launch_bounds__(256) void k_adj_state(const double* __restrict__ f,
     kst[2 * n + c] = q.Ky;
     kst[3 * n + c] = q.KE;
     lam0[c] = q.rest;
+}
+
+// ---------------------------------------------------------------------------
+// Marching reverse step (after the state pass). One wavefront takes one
+// moving velocity i over a strip of 64 columns and a chunk of rows of the
+// region whose stencils need no ghost cell (adj_rect); the tiles around it go
+// to k_adjoint in band mode. Along x the lanes are canonical, i.e. seen from
+// the upwind side: lane l holds canonical column l (natural column X0 + l,
+// or X0 + 63 - l for v_x < 0), so that the face between canonical columns c
+// and c+1 has the samples c-2..c+2 and feeds the cells c-2..c+2. Along y
+// every wave walks the natural rows upwards, whatever the sign of v_y: step
+// t completes row Y0 - 4 + t, for all velocities alike, so that the waves
+// of a region read the same rows of the K planes and of the neighbouring
+// strips at about the same time.
+//  - y faces: each lane carries the sliding differences of the forward WENO
+//    of the five rows Y0-4+t .. Y0+t of its column in upwind order; step t
+//    evaluates the face between rows Y0-2+t and Y0-1+t (v_y > 0, samples
+//    upwards from row Y0-4+t) or between rows Y0-3+t and Y0-2+t (v_y < 0,
+//    samples downwards from row Y0+t), the last face that reaches row
+//    Y0-4+t. Every y face is evaluated once, four of them ahead of the chunk.
+//  - x faces: the completed row is exchanged through LDS; lane l evaluates
+//    the face between canonical columns l and l+1 and the five
+//    contributions of each face are gathered back through LDS. The four
+//    faces beyond the strip's edges (canonical faces -2, -1, 64, 65), which
+//    reach the cells 0, 1, 62 and 63, are saved per row and evaluated for a
+//    batch of MB rows at once, one lane per face and row; those four cells
+//    are written then.
+// Loads run two steps ahead, each into the register it frees.
+constexpr int MB = 16;
+
+struct MarchLds {
+    double P[72];           // v_x f of the row, canonical columns -4..67
+    double L[72];           // lambda' of the row, canonical columns -4..67 (-2..66 used)
+    double G[4][68];        // G_0, G_1, G_3, G_4 of canonical faces -2..65 (-2, -1, 64, 65: 0)
+    double ring[MB][18];    // per row: P(-4..1), P(62..67), L(-2..0), L(64..66)
+    double part[MB][4][2];  // cells 0, 1, 62, 63: output without the x term, partial x sum
+    double eg[64][2];       // contributions of the edge faces
+    double dump[64][2];     // where the lanes without a value to save write theirs
+};
+
+// mu dh/dP_q (q = 0..4) of one face from its five upwind-ordered samples; the
+// centre sample's own term mu is included.
+__device__ __forceinline__ void face_g5(double P0, double P1, double P2, double P3, double P4,
+                                        double eps, double mu, double (&G)[5])
+{
+    constexpr double C13 = 13.0 / 12.0;
+    const double g[4] = {P1 - P0, P2 - P1, P3 - P2, P4 - P3};
+    const double D[3] = {g[1] - g[0], g[2] - g[1], g[3] - g[2]};
+    const double E[3] = {__builtin_fma(C13 * D[0], D[0], eps), __builtin_fma(C13 * D[1], D[1], eps),
+                         __builtin_fma(C13 * D[2], D[2], eps)};
+    double Gg[4];
+    weno_face_bar_g(g, D, E, mu, Gg);
+    G[0] = -Gg[0];
+    G[1] = Gg[0] - Gg[1];
+    G[2] = (Gg[1] - Gg[2]) + mu;
+    G[3] = Gg[2] - Gg[3];
+    G[4] = Gg[3];
+}
+
+// The marching workgroup is one wavefront, and the LDS carries out one
+// wavefront's accesses in the order they are issued: a read issued after a
+// write of another lane sees it. Only the compiler has to keep the accesses
+// in program order across these points.
+__device__ __forceinline__ void wave_lds_order() { asm volatile("" ::: "memory"); }
+
+// Raw buffer access to planes below 2 GiB in all: the row (and plane)
+// offset goes in the scalar offset, the lane's column in the vector offset.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const double* p, int64_t cells)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), 0, (int)(cells * 8),
+                                             0x00020000);
+}
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned voff,
+                                       unsigned soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r, voff, soff, 0);
+}
+
+template <bool HASY, bool NEGY>
+__device__ __forceinline__ void march_velocity(const AdjArgs& a, MarchLds& s, int i, int X0, int Y0,
+                                               int H, int lane)
+{
+    constexpr double C13 = 13.0 / 12.0;
+    const int nx = a.nx;
+    const int64_t plane = (int64_t)nx * a.ny;
+    const double vx = a.k.vx[i], vy = a.k.vy[i], hv2 = a.k.hv2[i];
+    const bool negx = vx < 0.0;
+    const double cnx = negx ? -a.cx : a.cx, cy = a.cy;
+    const double eps = a.k.eps, omct = 1.0 - a.ct;
+    // natural column of canonical column c (c in -4..67: one period at most
+    // away, which happens on a periodic x axis only)
+    auto colc = [&](int c) {
+        int x = negx ? X0 + 63 - c : X0 + c;
+        x = x < 0 ? x + nx : x;
+        return x >= nx ? x - nx : x;
+    };
+    // byte offset of row Y0 - 4 + t (t in 0..H+7: the marched rows are at
+    // least four rows from either end)
+    const int rowbytes = nx * 8, base = (Y0 - 4) * rowbytes;
+    auto rowt = [&](int t) { return (unsigned)(base + t * rowbytes); };
+    const unsigned co = 8u * (unsigned)colc(lane);
+    // extra samples of the edge faces: f at canonical -4..-1 and 64..67
+    // (lanes 0..7), lambda' at -2, -1, 64, 65, 66 (lanes 0..4)
+    const unsigned cxf = 8u * (unsigned)colc(lane < 4 ? lane - 4 : lane < 8 ? 60 + lane : lane);
+    const unsigned cxl = 8u * (unsigned)colc(lane < 2 ? lane - 2 : lane < 5 ? 62 + lane : lane);
+    const __amdgpu_buffer_rsrc_t rf = plane_rsrc(a.f + i * plane, plane);
+    const __amdgpu_buffer_rsrc_t rl = plane_rsrc(a.lam1 + i * plane, plane);
+    const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.lam0 + i * plane, plane);
+    // the K planes of the output (one resource for the four planes, the
+    // plane in the scalar offset)
+    const __amdgpu_buffer_rsrc_t rk = plane_rsrc(a.kst, 4 * plane);
+    const unsigned pb = (unsigned)(plane * 8);
+    auto kload = [&](int q, unsigned col, unsigned row) { return bload(rk, col, row + q * pb); };
+    // per-lane LDS slots (lanes with nothing to save write to s.dump): the
+    // edge samples' destinations, the ring's sources and destinations, the
+    // saved outputs of cells 0, 1, 62 and 63
+    double* const dxf = lane < 8 ? s.P + (lane < 4 ? lane : 64 + lane) : &s.dump[lane][0];
+    double* const dxl = lane < 5 ? s.L + (lane < 2 ? lane + 2 : 66 + lane) : &s.dump[lane][1];
+    const double* const rsrc = lane < 6    ? s.P + lane
+                               : lane < 12 ? s.P + 60 + lane
+                               : lane < 15 ? s.L + lane - 10
+                               : lane < 18 ? s.L + 53 + lane
+                                           : s.P;
+    double* const rdst = lane < 18 ? &s.ring[0][lane] : &s.dump[lane][0];
+    const int rstride = lane < 18 ? 18 : 0;
+    const bool edge = lane < 2 || lane >= 62;
+    double* const pdst = edge ? &s.part[0][lane < 2 ? lane : lane - 60][0] : &s.dump[lane][0];
+    const int pstride = edge ? 8 : 0;
+
+    if (lane < 4) {
+        s.G[lane][0] = s.G[lane][1] = 0.0;
+        s.G[lane][66] = s.G[lane][67] = 0.0;
+    }
+    // state at step t: L = lambda' of rows Y0-4+t .. Y0-1+t, Acc[j] = the y
+    // sum of row Y0-4+t+j so far (j < 4); g: the first differences of the
+    // face's samples v_y f (rows Y0-4+t .. Y0+t) in upwind order, slid from
+    // step to step (the second differences and smoothness terms are formed
+    // from them in each face); Pl: v_y f of row Y0+t
+    double L[4], Acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double Pl = 0.0, g[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) L[q] = bload(rl, co, rowt(q));
+    if constexpr (HASY) {
+        double F[5], P[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) F[q] = bload(rf, co, rowt(q));
+#pragma unroll
+        for (int q = 0; q < 5; ++q) P[q] = vy * F[NEGY ? 4 - q : q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g[q] = P[q + 1] - P[q];
+        Pl = P[NEGY ? 0 : 4];
+    }
+    // slot k = t mod 2 holds what step t consumes: f of row Y0+1+t,
+    // lambda' of row Y0+t and, for the x pass of row Y0-4+t, f of the lane
+    // and of the edge samples and the K's; the loads run two steps ahead
+    double fb[2], lb[2], xfo[2], xfb[2], xlb[2], kb[2][4];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        fb[k] = bload(rf, co, rowt(5 + k));
+        lb[k] = bload(rl, co, rowt(4 + k));
+        xfo[k] = xfb[k] = xlb[k] = 0.0;
+        kb[k][0] = kb[k][1] = kb[k][2] = kb[k][3] = 0.0;
+    }
+
+    auto face = [&](auto kc, auto outc, int t) {
+        constexpr int k = decltype(kc)::value;
+        constexpr bool OUT = decltype(outc)::value;
+        const unsigned r = (unsigned)(t - 4), rr = r % MB;  // output row Y0 + r
+        if constexpr (OUT) {
+            // the completed row into LDS for its x faces
+            s.P[lane + 4] = vx * xfo[k];
+            s.L[lane + 4] = L[0];
+            *dxf = vx * xfb[k];
+            *dxl = xlb[k];
+        }
+        double Gl = 0.0;  // the contribution to the row entering the window
+        if constexpr (HASY) {
+            // v_y > 0: the face between rows Y0-2+t and Y0-1+t, samples rows
+            // Y0-4+t.. upwards; v_y < 0: between rows Y0-3+t and Y0-2+t,
+            // samples rows Y0+t.. downwards
+            const double mu = NEGY ? cy * (L[2] - L[1]) : cy * (L[3] - L[2]);
+            const double D[3] = {g[1] - g[0], g[2] - g[1], g[3] - g[2]};
+            const double E[3] = {__builtin_fma(C13 * D[0], D[0], eps),
+                                 __builtin_fma(C13 * D[1], D[1], eps),
+                                 __builtin_fma(C13 * D[2], D[2], eps)};
+            double Gg[4];
+            weno_face_bar_g(g, D, E, mu, Gg);
+            const double G0 = -Gg[0], G1 = Gg[0] - Gg[1], G2 = (Gg[1] - Gg[2]) + mu,
+                         G3 = Gg[2] - Gg[3], G4 = Gg[3];
+            if constexpr (NEGY) {  // sample q is row Y0+t-q
+                Acc[0] += G4;
+                Acc[1] += G3;
+                Acc[2] += G2;
+                Acc[3] += G1;
+                Gl = G0;
+            } else {  // sample q is row Y0-4+t+q
+                Acc[0] += G0;
+                Acc[1] += G1;
+                Acc[2] += G2;
+                Acc[3] += G3;
+                Gl = G4;
+            }
+        }
+        double out = 0.0, Gx2 = 0.0;
+        if constexpr (OUT) {
+            wave_lds_order();
+            const double* Pp = s.P + lane + 2;
+            const double mux = cnx * (s.L[lane + 5] - L[0]);
+            double Gx[5];
+            face_g5(Pp[0], Pp[1], Pp[2], Pp[3], Pp[4], eps, mux, Gx);
+            rdst[rr * rstride] = *rsrc;
+            s.G[0][lane + 2] = Gx[0];
+            s.G[1][lane + 2] = Gx[1];
+            s.G[2][lane + 2] = Gx[3];
+            s.G[3][lane + 2] = Gx[4];
+            Gx2 = Gx[2];
+            out = __builtin_fma(omct, L[0], kb[k][0]);
+            out = __builtin_fma(kb[k][1], vx, out);
+            out = __builtin_fma(kb[k][2], vy, out);
+            out = __builtin_fma(kb[k][3], hv2, out);
+            if constexpr (HASY) out = __builtin_fma(vy, Acc[0], out);
+        }
+        // slide to step t+1, consuming slot k
+#pragma unroll
+        for (int q = 0; q < 3; ++q) L[q] = L[q + 1];
+        L[3] = lb[k];
+        if constexpr (HASY) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) Acc[q] = Acc[q + 1];
+            Acc[3] = Gl;
+            const double Pn = vy * fb[k];
+            if constexpr (NEGY) {  // the new row is the first sample
+                g[3] = g[2];
+                g[2] = g[1];
+                g[1] = g[0];
+                g[0] = Pl - Pn;
+            } else {  // the new row is the last sample
+#pragma unroll
+                for (int q = 0; q < 3; ++q) g[q] = g[q + 1];
+                g[3] = Pn - Pl;
+            }
+            Pl = Pn;
+        }
+        // refill slot k for step t+2
+        fb[k] = bload(rf, co, rowt(min(t + 7, H + 7)));
+        lb[k] = bload(rl, co, rowt(min(t + 6, H + 6)));
+        {
+            const unsigned rx = rowt(min(t + 2, H + 3));
+            xfo[k] = bload(rf, co, rx);
+            xfb[k] = bload(rf, cxf, rx);
+            xlb[k] = bload(rl, cxl, rx);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) kb[k][q] = kload(q, co, rx);
+        }
+        if constexpr (OUT) {
+            wave_lds_order();
+            const double xs = ((s.G[0][lane + 4] + s.G[1][lane + 3]) + Gx2) +
+                              (s.G[2][lane + 1] + s.G[3][lane]);
+            pdst[rr * pstride] = out;
+            pdst[rr * pstride + 1] = xs;
+            if (!edge) bstore(__builtin_fma(vx, xs, out), ro, co, rowt(t));
+            wave_lds_order();
+        }
+    };
+
+    // the four steps ahead of the chunk's first row
+    face(std::integral_constant<int, 0>{}, std::false_type{}, 0);
+    face(std::integral_constant<int, 1>{}, std::false_type{}, 1);
+    face(std::integral_constant<int, 0>{}, std::false_type{}, 2);
+    face(std::integral_constant<int, 1>{}, std::false_type{}, 3);
+    // the strip-edge faces of the rows since the last batch, done = output
+    // rows so far
+    auto flush = [&](int done) {
+        const int nrows = done - (done - 1) / MB * MB, r0 = done - nrows;
+        const int rr = lane >> 2, e = lane & 3;
+        double c0 = 0.0, c1 = 0.0;
+        if (rr < nrows) {
+            const double* Rw = s.ring[rr];
+            const int b0 = e < 2 ? e : 4 + e;
+            const int lo = e < 2 ? 12 + e : 13 + e;
+            const double mu = cnx * (Rw[lo + 1] - Rw[lo]);
+            double Ge[5];
+            face_g5(Rw[b0], Rw[b0 + 1], Rw[b0 + 2], Rw[b0 + 3], Rw[b0 + 4], eps, mu, Ge);
+            // face -2 -> cell 0: G_4; face -1 -> cells 0, 1: G_3, G_4;
+            // face 64 -> cells 62, 63: G_0, G_1; face 65 -> cell 63: G_0
+            c0 = e == 0 ? Ge[4] : e == 1 ? Ge[3] : Ge[0];
+            c1 = e == 1 ? Ge[4] : e == 2 ? Ge[1] : 0.0;
+        }
+        s.eg[lane][0] = c0;
+        s.eg[lane][1] = c1;
+        wave_lds_order();
+        if (rr < nrows) {
+            const int b = 4 * rr;
+            const double add = e == 0   ? s.eg[b][0] + s.eg[b + 1][0]
+                               : e == 1 ? s.eg[b + 1][1]
+                               : e == 2 ? s.eg[b + 2][0]
+                                        : s.eg[b + 2][1] + s.eg[b + 3][0];
+            const int cell = e < 2 ? e : 60 + e;
+            // (the row differs between lanes: it goes in the vector offset)
+            bstore(__builtin_fma(vx, s.part[rr][e][1] + add, s.part[rr][e][0]), ro,
+                   rowt(r0 + rr + 4) + 8u * (unsigned)colc(cell), 0u);
+        }
+        wave_lds_order();
+    };
+
+    // Eight steps per trip: a loaded value lives at most six steps (two in
+    // its slot, four in the window), so every load of the body keeps one
+    // register from trip to trip and none is copied at the loop head.
+    const int nblk = H / 4;
+    int bk = 0;
+#pragma unroll 1
+    for (; bk + 2 <= nblk; bk += 2) {
+        const int p0 = __builtin_amdgcn_readfirstlane(4 + 4 * bk);
+        face(std::integral_constant<int, 0>{}, std::true_type{}, p0);
+        face(std::integral_constant<int, 1>{}, std::true_type{}, p0 + 1);
+        face(std::integral_constant<int, 0>{}, std::true_type{}, p0 + 2);
+        face(std::integral_constant<int, 1>{}, std::true_type{}, p0 + 3);
+        face(std::integral_constant<int, 0>{}, std::true_type{}, p0 + 4);
+        face(std::integral_constant<int, 1>{}, std::true_type{}, p0 + 5);
+        face(std::integral_constant<int, 0>{}, std::true_type{}, p0 + 6);
+        face(std::integral_constant<int, 1>{}, std::true_type{}, p0 + 7);
+        const int done = 4 * bk + 8;  // a multiple of 8: the ring holds MB = 16 rows
+        if (done % MB == 0 || bk + 2 == nblk) flush(done);
+    }
+    if (bk < nblk) {
+        const int p0 = 4 + 4 * bk;
+        face(std::integral_constant<int, 0>{}, std::true_type{}, p0);
+        face(std::integral_constant<int, 1>{}, std::true_type{}, p0 + 1);
+        face(std::integral_constant<int, 0>{}, std::true_type{}, p0 + 2);
+        face(std::integral_constant<int, 1>{}, std::true_type{}, p0 + 3);
+        flush(4 * bk + 4);
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_adj_march(AdjArgs a)
+{
+    __shared__ MarchLds s;
+    const int b = blockIdx.x;
+    const int work = (b & 7) * a.per_xcd + (b >> 3);
+    if (work >= a.nwork) return;
+    const int reg = work / 18;
+    const int i = 1 + (work - reg * 18);
+    const int chunk = reg / a.nstrip, strip = reg - chunk * a.nstrip;
+    const int X0 = (a.rect.c0 + strip) * ATX;
+    const int Y0 = a.rect.r0 * 4 + chunk * a.mh;
+    const int H = min(a.mh, a.rect.r1 * 4 - Y0);
+    const double vy = a.k.vy[i];
+    if (vy > 0.0)
+        march_velocity<true, false>(a, s, i, X0, Y0, H, threadIdx.x);
+    else if (vy < 0.0)
+        march_velocity<true, true>(a, s, i, X0, Y0, H, threadIdx.x);
+    else
+        march_velocity<false, false>(a, s, i, X0, Y0, H, threadIdx.x);
+}
+
+// The region the marching kernel takes, in tiles of 64 x 4 cells: along x
+// the whole tiles of a periodic axis (the stencils wrap), else the tiles whose
+// cells are at least four cells (the reach of a face's stencil plus one)
+// from either end, so that no stencil reaches a ghost cell and no wall term
+// applies; along y always the latter, so that no row index wraps.
+FastRect adj_rect(int nx, int ny, const int bc[4])
+{
+    FastRect r;
+    const int ty = (ny + 3) / 4;
+    if (bc[XLO] == PERIODIC) {
+        r.c0 = 0;
+        r.c1 = nx / ATX;
+    } else {
+        r.c0 = 1;
+        r.c1 = nx >= 4 ? (nx - 4) / ATX : 0;
+    }
+    // (on a periodic y axis too, so that the marched rows never wrap)
+    r.r0 = 1;
+    r.r1 = bc[YLO] == PERIODIC ? ny / 4 - 1 : ny >= 4 ? (ny - 4) / 4 : 0;
+    if (r.c1 <= r.c0 || r.r1 <= r.r0) {
+        r.c0 = r.c1 = 0;
+        r.r0 = r.r1 = ty;
+    }
+    return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -690,20 +1079,25 @@ __global__ __launch_bounds__(256) void k_rowdot(const double* __restrict__ A,
 // ---------------------------------------------------------------------------
 // Reverse-step variants: rows per lane R, velocity groups G, waves-per-SIMD
 // target W and whether a state pass forms the K's first (PS).
+// PS = 2: the state pass, then k_adj_march over adj_rect in chunks of R
+// rows and k_adjoint<4, 18, 2, true> in band mode around it.
 struct AdjVariant {
     int R, G, W, PS;
     void (*kernel)(AdjArgs);
 };
 
 #define LBM_ADJ_VARIANT(R, G, W, PS) {R, G, W, PS, k_adjoint<R, G, W, PS>},
+#define LBM_ADJ_MARCH(R, W) {R, 18, W, 2, k_adj_march<W>},
 // (no variant may spill registers: multi-plane groups under the two-wave
 // budget, and one velocity group per tile, are left out for that)
 static const AdjVariant kAdjVariants[] = {
     LBM_ADJ_VARIANT(4, 3, 1, 0) LBM_ADJ_VARIANT(4, 6, 1, 0)
     LBM_ADJ_VARIANT(4, 18, 1, 1) LBM_ADJ_VARIANT(4, 18, 2, 1) LBM_ADJ_VARIANT(2, 18, 2, 1)
     LBM_ADJ_VARIANT(4, 6, 1, 1) LBM_ADJ_VARIANT(4, 3, 1, 1)
+    LBM_ADJ_MARCH(64, 2) LBM_ADJ_MARCH(128, 2) LBM_ADJ_MARCH(256, 2)
 };
 #undef LBM_ADJ_VARIANT
+#undef LBM_ADJ_MARCH
 constexpr int kNumAdjVariants = sizeof(kAdjVariants) / sizeof(kAdjVariants[0]);
 
 int adj_variant_count() { return kNumAdjVariants; }
@@ -745,6 +1139,32 @@ hipError_t launch_adjoint(int variant, const double* f, const double* lam1, doub
                            lam1, lam0, kst, n, ct, wdxdy, k);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+    }
+    if (V.PS == 2) {
+        // band tiles (64 x 4, one velocity each), then the marched region;
+        // grids whose 4 K planes reach 2 GiB (32-bit buffer offsets) are all
+        // band
+        a.tiles_y = (ny + 3) / 4;
+        a.rect = adj_rect(nx, ny, bc);
+        if ((int64_t)nx * ny * 32 > INT32_MAX) {
+            a.rect.c0 = a.rect.c1 = 0;
+            a.rect.r0 = a.rect.r1 = a.tiles_y;
+        }
+        const int nband = band_count(a.rect, a.tiles_x, a.tiles_y);
+        if (nband > 0) {
+            a.nwork = nband * 18;
+            a.per_xcd = (a.nwork + 7) / 8;
+            hipLaunchKernelGGL((k_adjoint<4, 18, 2, true, true>), dim3(8 * a.per_xcd), dim3(64), 0,
+                               st, a);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        if (a.rect.c1 <= a.rect.c0) return hipSuccess;
+        a.mh = V.R;
+        a.nstrip = a.rect.c1 - a.rect.c0;
+        a.nchunk = ((a.rect.r1 - a.rect.r0) * 4 + V.R - 1) / V.R;
+        a.nwork = a.nstrip * a.nchunk * 18;
+        a.per_xcd = (a.nwork + 7) / 8;
     }
     hipLaunchKernelGGL(V.kernel, dim3(8 * a.per_xcd), dim3(64), 0, st, a);
     return hipGetLastError();

@@ -515,14 +515,15 @@ int lbm_tune_step(lbm_ctx* c, const double* f_in, double* f_tmp, int32_t nsteps,
 }
 
 // Default reverse-step variant: one velocity per workgroup after a state
-// pass, so that small grids still fill the chip.
+// pass, so that small grids still fill the chip; from 2^20 cells on, the
+// marching variant in chunks of 64 rows.
 int lbmi_default_adj_variant(int64_t cells)
 {
-    (void)cells;
+    const int want[4] = {cells >= (1 << 20) ? 64 : 4, 18, 2, cells >= (1 << 20) ? 2 : 1};
     for (int v = 0; v < adj_variant_count(); ++v) {
         int d[4];
         adj_variant_desc(v, d);
-        if (d[0] == 4 && d[1] == 18 && d[2] == 2 && d[3] == 1) return v;
+        if (d[0] == want[0] && d[1] == want[1] && d[2] == want[2] && d[3] == want[3]) return v;
     }
     return 0;
 }

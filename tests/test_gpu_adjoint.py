@@ -31,7 +31,10 @@ CASES = [((67, 45), (P, P, P, P)), ((67, 45), (P, P, R, R)), ((130, 37), (R, R, 
          ((70, 41), (F, F, P, P)), ((69, 43), (R, R, R, R)), ((9, 7), (R, R, R, R)),
          ((5, 6), (P, P, R, R)), ((3, 4), (R, R, P, P)), ((2, 3), (P, P, P, P)),
          # wider than one strip of the tile walk (8 tiles)
-         ((600, 21), (P, P, R, R)), ((1090, 9), (R, R, P, P))]
+         ((600, 21), (P, P, R, R)), ((1090, 9), (R, R, P, P)),
+         # marched strips between x walls, a ragged last chunk (68 rows in
+         # chunks of 64), a periodic x axis one strip wide
+         ((200, 50), (R, R, F, F)), ((140, 72), (F, F, P, P)), ((64, 30), (P, P, P, P))]
 
 
 def _state(nx, ny, seed):
