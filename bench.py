@@ -426,63 +426,56 @@ def _bench_line(log_path, key):
 def summarize_adjoint(trace, fetch, write, log_path, commands):
     """Markdown summary of the reverse-step profile: the kernel trace of
     `bench.py --only adjoint` and FETCH_SIZE / WRITE_SIZE passes of
-    `bench.py --pmc-run --only adjoint --variant 3` (2048^2, (4, 18, 1, true))."""
-    k_adj, k_st = "lbmd::k_adjoint<4, 18, 1, true>", "lbmd::k_adj_state"
-    tab = _capture(trace_table, trace, ["k_adjoint", "k_adj_state"])
-    ftab = _capture(counter_table, fetch, ["k_adjoint", "k_adj_state", "copyBuffer"])
-    wtab = _capture(counter_table, write, ["k_adjoint", "k_adj_state", "copyBuffer"])
-    t, fr, wr = _table_rows(tab), _table_rows(ftab), _table_rows(wtab)
+    `bench.py --pmc-run --only adjoint --variant V` (ten 2048^2 reverse
+    steps of variant V: its state pass, band tiles and march or tile kernel)."""
+    tab = _capture(trace_table, trace, ["k_adj"])
+    ftab = _capture(counter_table, fetch, ["k_adj", "copyBuffer"])
+    wtab = _capture(counter_table, write, ["k_adj", "copyBuffer"])
+    fr, wr = _table_rows(ftab), _table_rows(wtab)
     n = 2048 * 2048
-    # medians: the traced command also runs the overlapped gradients
-    adj, st = float(t[(k_adj, 18874368)][4]), float(t[(k_st, 4194304)][4])
-    adj256, st256 = float(t[(k_adj, 294912)][4]), float(t[(k_st, 65536)][4])
     sf = COPY_BYTES / (float(fr[("__amd_rocclr_copyBuffer", 131072)][4]) * 1024)
     sw = COPY_BYTES / (float(wr[("__amd_rocclr_copyBuffer", 131072)][4]) * 1024)
-    f_adj = float(fr[(k_adj, 18874368)][4]) * 1024 * sf / n
-    f_st = float(fr[(k_st, 4194304)][4]) * 1024 * sf / n
-    w_adj = float(wr[(k_adj, 18874368)][4]) * 1024 * sw / n
-    w_st = float(wr[(k_st, 4194304)][4]) * 1024 * sw / n
-    tot = f_adj + f_st + w_adj + w_st
+    per = []
+    for (name, grid), row in sorted(fr.items()):
+        if "k_adj" not in name:
+            continue
+        w = wr.get((name, grid))
+        per.append((name, float(row[4]) * 1024 * sf / n,
+                    float(w[4]) * 1024 * sw / n if w else 0.0))
+    rd, wt = sum(p[1] for p in per), sum(p[2] for p in per)
     ev = _bench_line(log_path, "adjoint")
+    r2048, r256 = ev["reverse_step_2048"], ev["reverse_step_256"]
     lines = [
         "# Reverse step (discrete adjoint), shear layer at 256^2 and 2048^2: durations and HBM traffic",
         "",
-        "kernels: lbmd::k_adjoint<R, G, W, PS> (+ lbmd::k_adj_state for PS = true); the tuner "
-        "picks (4, 18, 1, true) or (4, 18, 2, true)",
+        "Variants (R, G, W, PS): PS = 1 runs lbmd::k_adj_state, then lbmd::k_adjoint<R, G, W, true> "
+        "over 64 x R tiles; PS = 2 runs lbmd::k_adj_state, lbmd::k_adjoint<4, 18, 2, true, true> "
+        "over the tiles next to the walls, and lbmd::k_adj_march<W> over 64-column strips in "
+        "chunks of R rows. The bench's tuner picked "
+        f"{tuple(r2048['variant'])} at 2048^2 ({r2048['MLUPS']:.0f} MLUPS, "
+        f"{1e6 * n / (r2048['MLUPS'] * 1e6):.0f} us per reverse step) and "
+        f"{tuple(r256['variant'])} at 256^2 ({r256['MLUPS']:.0f} MLUPS).",
         "",
-        "## Kernel trace (every adjoint variant the tuner tries, per grid size)",
+        "## Kernel trace (every variant the tuner tries, both sizes, and the gradients' steps)",
         "",
-        "Grid sizes: 294912 / 18874368 work-items are the 256^2 / 2048^2 reverse steps of the "
-        "(4, 18, *) variants; 65536 / 4194304 those of the per-cell state pass.",
+        "Medians: the traced command also runs the checkpointed gradients, whose reverse steps "
+        "overlap the recompute on a second stream.",
         "", tab, "",
-        "Medians, since the traced command also runs the checkpointed gradients, whose reverse "
-        "steps overlap the recompute on a second stream and take longer per dispatch (they pull "
-        f"the means up). Variant (4, 18, 1, true): 2048^2 {adj:.1f} + {st:.1f} = {adj + st:.1f} us "
-        f"per reverse step, i.e. {n / (adj + st):.0f} MLUPS (the bench's events in the same run: "
-        f"{ev['reverse_step_2048']['MLUPS']:.0f}); 256^2 {adj256:.1f} + {st256:.1f} = "
-        f"{adj256 + st256:.1f} us, i.e. {65536 / (adj256 + st256):.0f} MLUPS (events: "
-        f"{ev['reverse_step_256']['MLUPS']:.0f}, with the tuner's pick of that run, "
-        f"{tuple(ev['reverse_step_256']['variant'])}).",
-        "",
-        "## Counter passes, 2048^2, variant (4, 18, 1, true), ten reverse steps",
+        "## Counter passes, 2048^2, ten reverse steps of the profiled variant",
         "", "FETCH_SIZE (KiB per dispatch):", "", ftab, "",
         "WRITE_SIZE (KiB per dispatch):", "", wtab, "",
         f"Scale factors from the 512 MiB copy in the same runs: FETCH {sf:.4f}, WRITE {sw:.4f}.",
         "",
         "| kernel | read B/cell | written B/cell |",
         "|---|---|---|",
-        f"| k_adjoint<4, 18, 1, true> | {f_adj:.0f} | {w_adj:.0f} |",
-        f"| k_adj_state | {f_st:.0f} | {w_st:.0f} |",
-        f"| reverse step | {f_adj + f_st:.0f} | {w_adj + w_st:.0f} |",
+    ] + [f"| `{nm}` | {r:.0f} | {w:.0f} |" for nm, r, w in per] + [
+        f"| reverse step | {rd:.0f} | {wt:.0f} |",
         "",
-        f"Total {tot:.0f} B per cell against the algorithmic 456 (f^n and lambda^(n+1) read once, "
-        "lambda^n written once). The excess is the two-pass structure: the state pass reads f^n "
-        "and lambda^(n+1) in full and writes the four K planes and the rest plane; the plane "
-        "kernel then reads the 18 moving planes of both arrays again, with their halos, plus the "
-        f"K planes. Its {f_adj:.0f} B read per cell is close to that plane-kernel minimum "
-        "(2 x 144 + 32 = 320 B): halo rows shared by vertically adjacent tiles hit in L2. The "
-        f"state pass moves {f_st + w_st:.0f} B per cell in {st:.0f} us, "
-        f"{(f_st + w_st) * n / st / 1e3:.0f} GB/s.",
+        f"Total {rd + wt:.0f} B per cell against the algorithmic 456 (f^n and lambda^(n+1) read "
+        "once, lambda^n written once). The excess is the two-pass structure: the state pass "
+        "reads f^n and lambda^(n+1) in full (304 B) and writes the four K planes and the rest "
+        "plane (40 B); the velocity kernels then read the 18 moving planes of both arrays again "
+        "with their halo rows and strip-edge columns, plus the K planes.",
         "",
         "Commands (repository root, TMPDIR=/tmp):",
     ] + ["    " + c for c in commands]
@@ -549,15 +542,16 @@ def counter_table(root, match):
 # ---------------------------------------------------------------------------
 def pmc_run(args):
     """A short run for one rocprofv3 counter pass: the tuned main step (with
-    --only adjoint: ten 2048^2 reverse steps of variant --variant) and a
-    plain device copy of COPY_BYTES."""
+    --only adjoint: ten 2048^2 reverse steps of variant --variant, else of
+    the context's default) and a plain device copy of COPY_BYTES."""
     import torch
     from paper_1010_4124_amd import inputs, lbm, tune
     if args.only == "adjoint":
         s = inputs.khi(2048, 2048, Dv=0.01, Drho=0.04)
         ctx = lbm.Context.from_setup(s)
         f0 = ctx.init(*s.fields())
-        ctx.adj_variant = 0 if args.variant is None else args.variant
+        if args.variant is not None:
+            ctx.adj_variant = args.variant
         log(f"pmc run: reverse step variant {ctx.adj_variant} "
             f"{lbm.lbm_adjoint_variant_info(ctx.adj_variant)}")
         lam = [torch.randn_like(f0), ctx.empty_f()]

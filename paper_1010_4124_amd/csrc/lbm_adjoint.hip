@@ -652,7 +652,8 @@ struct MarchLds {
     double ring[MB][18];    // per row: P(-4..1), P(62..67), L(-2..0), L(64..66)
     double part[MB][4][2];  // cells 0, 1, 62, 63: output without the x term, partial x sum
     double eg[64][2];       // contributions of the edge faces
-    double dump[64][2];     // where the lanes without a value to save write theirs
+    double dump[4][64];     // where the lanes without a value to save write theirs (one row
+                            // per store, 8-byte lane stride: no bank conflicts)
 };
 
 // mu dh/dP_q (q = 0..4) of one face from its five upwind-ordered samples; the
@@ -735,17 +736,18 @@ __device__ __forceinline__ void march_velocity(const AdjArgs& a, MarchLds& s, in
     // per-lane LDS slots (lanes with nothing to save write to s.dump): the
     // edge samples' destinations, the ring's sources and destinations, the
     // saved outputs of cells 0, 1, 62 and 63
-    double* const dxf = lane < 8 ? s.P + (lane < 4 ? lane : 64 + lane) : &s.dump[lane][0];
-    double* const dxl = lane < 5 ? s.L + (lane < 2 ? lane + 2 : 66 + lane) : &s.dump[lane][1];
+    double* const dxf = lane < 8 ? s.P + (lane < 4 ? lane : 64 + lane) : &s.dump[0][lane];
+    double* const dxl = lane < 5 ? s.L + (lane < 2 ? lane + 2 : 66 + lane) : &s.dump[1][lane];
     const double* const rsrc = lane < 6    ? s.P + lane
                                : lane < 12 ? s.P + 60 + lane
                                : lane < 15 ? s.L + lane - 10
                                : lane < 18 ? s.L + 53 + lane
                                            : s.P;
-    double* const rdst = lane < 18 ? &s.ring[0][lane] : &s.dump[lane][0];
+    double* const rdst = lane < 18 ? &s.ring[0][lane] : &s.dump[2][lane];
     const int rstride = lane < 18 ? 18 : 0;
     const bool edge = lane < 2 || lane >= 62;
-    double* const pdst = edge ? &s.part[0][lane < 2 ? lane : lane - 60][0] : &s.dump[lane][0];
+    double* const pdst0 = edge ? &s.part[0][lane < 2 ? lane : lane - 60][0] : &s.dump[3][lane];
+    double* const pdst1 = edge ? pdst0 + 1 : &s.dump[0][lane];
     const int pstride = edge ? 8 : 0;
 
     if (lane < 4) {
@@ -877,8 +879,8 @@ __device__ __forceinline__ void march_velocity(const AdjArgs& a, MarchLds& s, in
             wave_lds_order();
             const double xs = ((s.G[0][lane + 4] + s.G[1][lane + 3]) + Gx2) +
                               (s.G[2][lane + 1] + s.G[3][lane]);
-            pdst[rr * pstride] = out;
-            pdst[rr * pstride + 1] = xs;
+            pdst0[rr * pstride] = out;
+            pdst1[rr * pstride] = xs;
             if (!edge) bstore(__builtin_fma(vx, xs, out), ro, co, rowt(t));
             wave_lds_order();
         }
