@@ -27,8 +27,9 @@ transition-layer studies on its own shear layer. `cpu_baseline` is the CPU
 oracle timed on a bounded sample of the main workload.
 
 Other modes (for the rocprofv3 runs whose summaries live in profiles/):
-  --pmc-run        a few steps of the main workload plus a 512 MiB device
-                   copy, for one counter pass
+  --pmc-run        a few steps of the main workload (with --only forward512:
+                   of the 512^2 one; --only adjoint: ten 2048^2 reverse
+                   steps) plus a 512 MiB device copy, for one counter pass
   --summarize ...  turn the kernel-trace and counter CSVs into the summary
   --only PART      run one of the other workloads alone (forward512, batch,
                    adjoint) and print its figures as one JSON line
@@ -560,16 +561,15 @@ def pmc_run(args):
         del ctx, f0, lam
         torch.cuda.empty_cache()
     else:
-        _pmc_main(args)
+        _pmc_main(args, small_setup() if args.only == "forward512" else main_setup())
     x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
     y.copy_(x)
     torch.cuda.synchronize()
 
 
-def _pmc_main(args):
+def _pmc_main(args, s):
     from paper_1010_4124_amd import lbm, tune
-    s = main_setup()
     ctx = lbm.Context.from_setup(s)
     f0 = ctx.init(*s.fields())
     if args.variant is None:
@@ -658,10 +658,10 @@ def summarize(args):
     w_k, w_c = per_dispatch(write, "WRITE_SIZE")
     sf, sw = COPY_BYTES / (f_c * 1024.0), COPY_BYTES / (w_c * 1024.0)
     traffic = f_k * 1024.0 * sf + w_k * 1024.0 * sw
-    cells = MAIN_N * MAIN_N
+    cells = args.n * args.n
     algo = BYTES_PER_LUP * cells
     lines = [
-        f"# Step kernel(s), {MAIN_N} x {MAIN_N} shear layer: duration and HBM traffic per step",
+        f"# Step kernel(s), {args.n} x {args.n} shear layer: duration and HBM traffic per step",
         "",
         f"kernel: {name}",
         f"source_sha1: {source_hash()}",
@@ -729,6 +729,8 @@ def main():
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE", "FETCH", "WRITE"))
     ap.add_argument("--commands", nargs="*")
     ap.add_argument("--sq", nargs="*", help="SQ counter-pass directories for --summarize")
+    ap.add_argument("--n", type=int, default=MAIN_N,
+                    help="--summarize: the side of the profiled grid (2048, or 512 for forward512)")
     ap.add_argument("--last", type=int, default=20,
                     help="--summarize: dispatches of the timed call (its last ones)")
     ap.add_argument("--only", choices=("forward512", "batch", "adjoint"))

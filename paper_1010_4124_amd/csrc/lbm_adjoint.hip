@@ -44,7 +44,8 @@ struct AdjArgs {
     const double* __restrict__ f;
     const double* __restrict__ lam1;
     double* __restrict__ lam0;
-    const double* __restrict__ kst;  // K0, Kx, Ky, KE planes (state-pass variants)
+    const double* __restrict__ kst;  // K0, Kx, Ky, KE of each cell, side by side (state-pass
+                                     // variants)
     int nx, ny;
     int bc[4];
     int tiles_x, tiles_y, nwork, per_xcd;
@@ -558,10 +559,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_
         if (!act) continue;
         const int64_t c = (int64_t)gy * a.nx + gx;
         if (PS) {
-            K0[m] = a.kst[c];
-            Kx[m] = a.kst[plane + c];
-            Ky[m] = a.kst[2 * plane + c];
-            KE[m] = a.kst[3 * plane + c];
+            K0[m] = a.kst[4 * c];
+            Kx[m] = a.kst[4 * c + 1];
+            Ky[m] = a.kst[4 * c + 2];
+            KE[m] = a.kst[4 * c + 3];
         } else {
             // loads at their point of use: these variants have no registers
             // to spare for 38 values in flight
@@ -610,10 +611,12 @@ __global__ __launch_bounds__(256) void k_adj_state(const double* __restrict__ f,
     __builtin_amdgcn_sched_barrier(0);
     const AdjCell q = adj_cell([&](int i) { return fv[i]; }, [&](int i) { return lv[i]; }, k, ct,
                                wdxdy);
-    kst[c] = q.K0;
-    kst[n + c] = q.Kx;
-    kst[2 * n + c] = q.Ky;
-    kst[3 * n + c] = q.KE;
+    // the four K's of a cell side by side (32 bytes): the marching kernel
+    // takes them with two 16-byte loads
+    kst[4 * c] = q.K0;
+    kst[4 * c + 1] = q.Kx;
+    kst[4 * c + 2] = q.Ky;
+    kst[4 * c + 3] = q.KE;
     lam0[c] = q.rest;
 }
 
@@ -640,9 +643,11 @@ __global__ __launch_bounds__(256) void k_adj_state(const double* __restrict__ f,
 //    contributions of each face are gathered back through LDS. The four
 //    faces beyond the strip's edges (canonical faces -2, -1, 64, 65), which
 //    reach the cells 0, 1, 62 and 63, are saved per row and evaluated for a
-//    batch of MB rows at once, one lane per face and row; those four cells
-//    are written then.
-// Loads run two steps ahead, each into the register it frees.
+//    batch of MB rows at once, one lane per face and row.
+// The output rows wait in LDS until their batch's edge faces are done and
+// are then written whole (full 128-byte lines). Loads run two steps ahead,
+// each into the register it frees; f is loaded once per row, for the y
+// window, and kept in registers until its row's x pass.
 constexpr int MB = 16;
 
 struct MarchLds {
@@ -652,6 +657,7 @@ struct MarchLds {
     double ring[MB][18];    // per row: P(-4..1), P(62..67), L(-2..0), L(64..66)
     double part[MB][4][2];  // cells 0, 1, 62, 63: output without the x term, partial x sum
     double eg[64][2];       // contributions of the edge faces
+    double orow[MB][64];    // the output rows of the batch, canonical columns
     double dump[4][64];     // where the lanes without a value to save write theirs (one row
                             // per store, 8-byte lane stride: no bank conflicts)
 };
@@ -722,17 +728,28 @@ __device__ __forceinline__ void march_velocity(const AdjArgs& a, MarchLds& s, in
     auto rowt = [&](int t) { return (unsigned)(base + t * rowbytes); };
     const unsigned co = 8u * (unsigned)colc(lane);
     // extra samples of the edge faces: f at canonical -4..-1 and 64..67
-    // (lanes 0..7), lambda' at -2, -1, 64, 65, 66 (lanes 0..4)
-    const unsigned cxf = 8u * (unsigned)colc(lane < 4 ? lane - 4 : lane < 8 ? 60 + lane : lane);
-    const unsigned cxl = 8u * (unsigned)colc(lane < 2 ? lane - 2 : lane < 5 ? 62 + lane : lane);
+    // (lanes 0..7), lambda' at -2, -1, 64, 65, 66 (lanes 0..4); the other
+    // lanes repeat the addresses of the first ones, so that each of these
+    // loads touches two cache lines
+    const int l8 = lane & 7, l4 = lane & 3;
+    const unsigned cxf = 8u * (unsigned)colc(l8 < 4 ? l8 - 4 : 60 + l8);
+    const unsigned cxl = 8u * (unsigned)colc(lane < 5 ? (lane < 2 ? lane - 2 : 62 + lane)
+                                                      : (l4 < 2 ? l4 - 2 : 62 + l4));
     const __amdgpu_buffer_rsrc_t rf = plane_rsrc(a.f + i * plane, plane);
     const __amdgpu_buffer_rsrc_t rl = plane_rsrc(a.lam1 + i * plane, plane);
     const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.lam0 + i * plane, plane);
-    // the K planes of the output (one resource for the four planes, the
-    // plane in the scalar offset)
+    // the K's of the output, 32 bytes per cell: two 16-byte loads per lane
     const __amdgpu_buffer_rsrc_t rk = plane_rsrc(a.kst, 4 * plane);
-    const unsigned pb = (unsigned)(plane * 8);
-    auto kload = [&](int q, unsigned col, unsigned row) { return bload(rk, col, row + q * pb); };
+    auto kload = [&](double (&K)[4], unsigned row) {
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        const u4 v0 = __builtin_amdgcn_raw_buffer_load_b128(rk, 4u * co, 4u * row, 0);
+        const u4 v1 = __builtin_amdgcn_raw_buffer_load_b128(rk, 4u * co + 16u, 4u * row, 0);
+        K[0] = __builtin_bit_cast(double, (u2){v0[0], v0[1]});
+        K[1] = __builtin_bit_cast(double, (u2){v0[2], v0[3]});
+        K[2] = __builtin_bit_cast(double, (u2){v1[0], v1[1]});
+        K[3] = __builtin_bit_cast(double, (u2){v1[2], v1[3]});
+    };
     // per-lane LDS slots (lanes with nothing to save write to s.dump): the
     // edge samples' destinations, the ring's sources and destinations, the
     // saved outputs of cells 0, 1, 62 and 63
@@ -758,15 +775,16 @@ __device__ __forceinline__ void march_velocity(const AdjArgs& a, MarchLds& s, in
     // sum of row Y0-4+t+j so far (j < 4); g: the first differences of the
     // face's samples v_y f (rows Y0-4+t .. Y0+t) in upwind order, slid from
     // step to step (the second differences and smoothness terms are formed
-    // from them in each face); Pl: v_y f of row Y0+t
+    // from them in each face); Pl: v_y f of row Y0+t; F = f of rows
+    // Y0-4+t .. Y0+t
     double L[4], Acc[4] = {0.0, 0.0, 0.0, 0.0};
-    double Pl = 0.0, g[4] = {0.0, 0.0, 0.0, 0.0};
+    double Pl = 0.0, g[4] = {0.0, 0.0, 0.0, 0.0}, F[5];
 #pragma unroll
     for (int q = 0; q < 4; ++q) L[q] = bload(rl, co, rowt(q));
-    if constexpr (HASY) {
-        double F[5], P[5];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) F[q] = bload(rf, co, rowt(q));
+    for (int q = 0; q < 5; ++q) F[q] = bload(rf, co, rowt(q));
+    if constexpr (HASY) {
+        double P[5];
 #pragma unroll
         for (int q = 0; q < 5; ++q) P[q] = vy * F[NEGY ? 4 - q : q];
 #pragma unroll
@@ -774,14 +792,14 @@ __device__ __forceinline__ void march_velocity(const AdjArgs& a, MarchLds& s, in
         Pl = P[NEGY ? 0 : 4];
     }
     // slot k = t mod 2 holds what step t consumes: f of row Y0+1+t,
-    // lambda' of row Y0+t and, for the x pass of row Y0-4+t, f of the lane
-    // and of the edge samples and the K's; the loads run two steps ahead
-    double fb[2], lb[2], xfo[2], xfb[2], xlb[2], kb[2][4];
+    // lambda' of row Y0+t and, for the x pass of row Y0-4+t, the edge
+    // samples and the K's; the loads run two steps ahead
+    double fb[2], lb[2], xfb[2], xlb[2], kb[2][4];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         fb[k] = bload(rf, co, rowt(5 + k));
         lb[k] = bload(rl, co, rowt(4 + k));
-        xfo[k] = xfb[k] = xlb[k] = 0.0;
+        xfb[k] = xlb[k] = 0.0;
         kb[k][0] = kb[k][1] = kb[k][2] = kb[k][3] = 0.0;
     }
 
@@ -791,7 +809,7 @@ __device__ __forceinline__ void march_velocity(const AdjArgs& a, MarchLds& s, in
         const unsigned r = (unsigned)(t - 4), rr = r % MB;  // output row Y0 + r
         if constexpr (OUT) {
             // the completed row into LDS for its x faces
-            s.P[lane + 4] = vx * xfo[k];
+            s.P[lane + 4] = vx * F[0];
             s.L[lane + 4] = L[0];
             *dxf = vx * xfb[k];
             *dxl = xlb[k];
@@ -847,6 +865,9 @@ __device__ __forceinline__ void march_velocity(const AdjArgs& a, MarchLds& s, in
 #pragma unroll
         for (int q = 0; q < 3; ++q) L[q] = L[q + 1];
         L[3] = lb[k];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) F[q] = F[q + 1];
+        F[4] = fb[k];
         if constexpr (HASY) {
 #pragma unroll
             for (int q = 0; q < 3; ++q) Acc[q] = Acc[q + 1];
@@ -869,11 +890,9 @@ __device__ __forceinline__ void march_velocity(const AdjArgs& a, MarchLds& s, in
         lb[k] = bload(rl, co, rowt(min(t + 6, H + 6)));
         {
             const unsigned rx = rowt(min(t + 2, H + 3));
-            xfo[k] = bload(rf, co, rx);
             xfb[k] = bload(rf, cxf, rx);
             xlb[k] = bload(rl, cxl, rx);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) kb[k][q] = kload(q, co, rx);
+            kload(kb[k], rx);
         }
         if constexpr (OUT) {
             wave_lds_order();
@@ -881,7 +900,7 @@ __device__ __forceinline__ void march_velocity(const AdjArgs& a, MarchLds& s, in
                               (s.G[2][lane + 1] + s.G[3][lane]);
             pdst0[rr * pstride] = out;
             pdst1[rr * pstride] = xs;
-            if (!edge) bstore(__builtin_fma(vx, xs, out), ro, co, rowt(t));
+            s.orow[rr][lane] = __builtin_fma(vx, xs, out);  // (edge cells: completed later)
             wave_lds_order();
         }
     };
@@ -920,9 +939,10 @@ __device__ __forceinline__ void march_velocity(const AdjArgs& a, MarchLds& s, in
                                         : s.eg[b + 2][1] + s.eg[b + 3][0];
             const int cell = e < 2 ? e : 60 + e;
             // (the row differs between lanes: it goes in the vector offset)
-            bstore(__builtin_fma(vx, s.part[rr][e][1] + add, s.part[rr][e][0]), ro,
-                   rowt(r0 + rr + 4) + 8u * (unsigned)colc(cell), 0u);
+            s.orow[rr][cell] = __builtin_fma(vx, s.part[rr][e][1] + add, s.part[rr][e][0]);
         }
+        wave_lds_order();
+        for (int q = 0; q < nrows; ++q) bstore(s.orow[q][lane], ro, co, rowt(r0 + q + 4));
         wave_lds_order();
     };
 
