@@ -424,11 +424,12 @@ def _bench_line(log_path, key):
         return json.loads(next(ln for ln in fh if ln.startswith('{"%s"' % key)))[key]
 
 
-def summarize_adjoint(trace, fetch, write, log_path, commands):
+def summarize_adjoint(trace, fetch, write, log_path, commands, sq_dirs=()):
     """Markdown summary of the reverse-step profile: the kernel trace of
     `bench.py --only adjoint` and FETCH_SIZE / WRITE_SIZE passes of
     `bench.py --pmc-run --only adjoint --variant V` (ten 2048^2 reverse
-    steps of variant V: its state pass, band tiles and march or tile kernel)."""
+    steps of variant V: its state pass, band tiles and march or tile kernel),
+    plus any further counter passes of the same command (sq_dirs)."""
     tab = _capture(trace_table, trace, ["k_adj"])
     ftab = _capture(counter_table, fetch, ["k_adj", "copyBuffer"])
     wtab = _capture(counter_table, write, ["k_adj", "copyBuffer"])
@@ -474,12 +475,46 @@ def summarize_adjoint(trace, fetch, write, log_path, commands):
         "",
         f"Total {rd + wt:.0f} B per cell against the algorithmic 456 (f^n and lambda^(n+1) read "
         "once, lambda^n written once). The excess is the two-pass structure: the state pass "
-        "reads f^n and lambda^(n+1) in full (304 B) and writes the four K planes and the rest "
+        "reads f^n and lambda^(n+1) in full (304 B) and writes the four K's and the rest "
         "plane (40 B); the velocity kernels then read the 18 moving planes of both arrays again "
-        "with their halo rows and strip-edge columns, plus the K planes.",
-        "",
-        "Commands (repository root, TMPDIR=/tmp):",
-    ] + ["    " + c for c in commands]
+        "with their halo rows and strip-edge columns, plus the K's.",
+    ]
+    if sq_dirs:
+        lines += ["", "## Further counter passes, 2048^2, the same ten reverse steps", ""]
+        vals = {}
+        for d in sq_dirs:
+            lines += [_capture(counter_table, d, ["k_adj"]), ""]
+            for r in _rows(os.path.join(d, "**", "*counter_collection.csv")):
+                if "k_adj" in _kname(r):
+                    vals.setdefault((_kname(r), int(r["Grid_Size"]), r["Counter_Name"]),
+                                    []).append(float(r["Counter_Value"]))
+        trows = _table_rows(tab)
+        for nm, grid in sorted({(k[0], k[1]) for k in vals}):
+            def get(c):
+                v = vals.get((nm, grid, c))
+                return statistics.mean(v) if v else None
+            parts = []
+            valu, waves, tr = get("SQ_INSTS_VALU"), get("SQ_WAVES"), trows.get((nm, grid))
+            if tr is not None and valu is not None and waves:
+                us = float(tr[4])
+                issue = valu * 4 / 1024 / 2.4e3
+                parts += [f"{valu / waves:.0f} VALU instructions per wave",
+                          f"VALU issue {issue:.0f} us per SIMD against the traced median "
+                          f"{us:.0f} us ({issue / us:.0%}; 4 cycles per wave64 instruction, "
+                          "1024 SIMDs, 2.4 GHz)"]
+            if get("SQ_WAIT_INST_ANY") and get("SQ_WAVE_CYCLES"):
+                parts.append(f"waiting on a dependency "
+                             f"{get('SQ_WAIT_INST_ANY') / get('SQ_WAVE_CYCLES'):.0%} of wave time")
+            if get("SQ_LDS_BANK_CONFLICT") is not None and get("SQ_ACTIVE_INST_LDS"):
+                parts.append(f"LDS bank conflicts "
+                             f"{get('SQ_LDS_BANK_CONFLICT') / get('SQ_ACTIVE_INST_LDS'):.0%} of "
+                             "LDS-active cycles")
+            if get("TCC_HIT_sum") is not None and get("TCC_MISS_sum"):
+                h, m = get("TCC_HIT_sum"), get("TCC_MISS_sum")
+                parts.append(f"L2 hits {h / (h + m):.0%} of requests")
+            if parts:
+                lines.append(f"- `{nm}` ({grid} work-items): " + "; ".join(parts) + ".")
+    lines += ["", "Commands (repository root, TMPDIR=/tmp):"] + ["    " + c for c in commands]
     print("\n".join(lines))
 
 
@@ -755,7 +790,7 @@ def main():
         counter_table(args.counter_table, args.match)
         return
     if args.summarize_adjoint:
-        summarize_adjoint(*args.summarize_adjoint, args.commands or [])
+        summarize_adjoint(*args.summarize_adjoint, args.commands or [], args.sq or [])
         return
     if args.summarize_batch:
         summarize_batch(*args.summarize_batch, args.commands or [])
