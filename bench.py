@@ -56,6 +56,9 @@ sys.path.insert(0, ROOT)
 
 BYTES_PER_LUP = 19 * 8 * 2          # forward: f^n read once, f^{n+1} written once
 ADJ_BYTES_PER_LUP = 19 * 8 * 3      # adjoint: f^n and lambda^{n+1} read, lambda^n written
+# adjoint given the moment sums of f^n: its 18 moving planes and the 4 sums
+# read instead of all 19 planes (the rest plane enters only through the sums)
+ADJ_SUMS_BYTES_PER_LUP = 18 * 8 + 4 * 8 + 19 * 8 * 2
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 512 << 20              # reference copy for the counter scale factors
 # counter summaries of the main workload's step, one per profiled variant
@@ -244,7 +247,21 @@ def bench_adjoint(args):
         res[f"reverse_step_{n}"] = {"MLUPS": mlups,
                                     "variant": list(lbm.lbm_adjoint_variant_info(ctx.adj_variant)),
                                     "hbm_frac": mlups * 1e6 * ADJ_BYTES_PER_LUP / 1e9 / HBM_PEAK_GBS}
-        del ctx, f0, lam
+        # the same given the moment sums of f^n (lbm_adjoint_step_sums), as
+        # the checkpointed gradient runs it with a fast-tile forward variant
+        sums = ctx.sums(f0)
+
+        def run_sums():
+            for q in range(steps):
+                ctx.adjoint_step(f0, lam[q % 2], 1e-5, out=lam[(q + 1) % 2], sums=sums)
+        run_sums()
+        secs, _ = sync_time(run_sums)
+        mlups = n * n * steps / secs / 1e6
+        res[f"reverse_step_{n}_sums"] = {
+            "MLUPS": mlups, "variant": list(lbm.lbm_adjoint_variant_info(ctx.adj_variant)),
+            "bytes_per_lup": ADJ_SUMS_BYTES_PER_LUP,
+            "hbm_frac": mlups * 1e6 * ADJ_SUMS_BYTES_PER_LUP / 1e9 / HBM_PEAK_GBS}
+        del ctx, f0, lam, sums
         torch.cuda.empty_cache()
     # full checkpointed gradient, 256^2 shear layer, 4000 steps, checkpoints every 200
     rng_amps = inputs.mode_amplitudes(256, seed=7)

@@ -124,6 +124,26 @@ int lbm_init(lbm_ctx* ctx, const double* rho, const double* ux, const double* uy
 int lbm_step(lbm_ctx* ctx, const double* f_in, double* f_out, int32_t nsteps,
              double* ke_log, lbm_stream stream);
 
+/* Moment sums of f per cell, the conserved quantities of Eq. (10): sums =
+ * [4][ny][nx] device doubles holding rho = sum_i f_i, j_x = sum_i f_i v_ix,
+ * j_y = sum_i f_i v_iy, E = sum_i f_i |v_i|^2 / 2 (= rho T + rho |u|^2 / 2),
+ * each summed over i = 0..18 in that order. sums must not overlap f. */
+int lbm_sums(lbm_ctx* ctx, const double* f, double* sums, lbm_stream stream);
+
+/* One step as lbm_step(f_in -> f_out, nsteps = 1, no energy log), carrying
+ * the moment sums: sums_in is NULL or the sums of f_in as lbm_sums or an
+ * earlier lbm_step_sums gave them, and sums_out receives the sums of f_out
+ * (layout of lbm_sums). With a carried-sum step variant (mode 1 or 3) the
+ * step reads sums_in instead of forming them from f_in and writes sums_out
+ * as it writes f_out (lbm_sums of f_out up to rounding; bit for bit for the
+ * fast-tile variants, mode 3, which sum in lbm_sums's order); with the
+ * others sums_out is lbm_sums of f_out. f_out is lbm_step's result bit for
+ * bit when sums_in is lbm_sums(f_in).
+ * For a sequence of single steps whose sums feed lbm_adjoint_step_sums.
+ * Outputs must not overlap the inputs or each other. */
+int lbm_step_sums(lbm_ctx* ctx, const double* f_in, const double* sums_in, double* f_out,
+                  double* sums_out, lbm_stream stream);
+
 /* (rho, ux, uy, T) of f per cell, Eq. (10): rho = sum f, rho u = sum f v,
  * rho T = sum f |v - u|^2 / 2. */
 int lbm_moments(lbm_ctx* ctx, const double* f, double* rho, double* ux, double* uy,
@@ -175,6 +195,14 @@ int lbm_check_state(lbm_ctx* ctx, const double* f, int64_t* out4, lbm_stream str
  * them). Deterministic: every output value is written once. */
 int lbm_adjoint_step(lbm_ctx* ctx, const double* f_n, const double* lam_np1, double w,
                      double* lam_n, lbm_stream stream);
+
+/* lbm_adjoint_step with the moment sums of f_n supplied (sums_n, layout of
+ * lbm_sums, not NULL): the variants with a per-cell pass (PS >= 1) take the
+ * equilibrium and objective terms from sums_n and lam_np1 without reading
+ * f_n a second time. With sums_n = lbm_sums(f_n) the result is
+ * lbm_adjoint_step's bit for bit. lam_n must not overlap any input. */
+int lbm_adjoint_step_sums(lbm_ctx* ctx, const double* f_n, const double* sums_n,
+                          const double* lam_np1, double w, double* lam_n, lbm_stream stream);
 
 /* Reverse-step variants (same role as the step variants). info4 = (R, G, W,
  * PS): tiles of 64 x R cells, the 18 moving velocities split into G groups

@@ -460,19 +460,12 @@ struct AdjCell {
     double K0, Kx, Ky, KE, rest;  // rest: the rest particle's adjoint
 };
 
-template <class FV, class LV>
-__device__ __forceinline__ AdjCell adj_cell(FV&& fv, LV&& lv, const Consts& k, double ct,
-                                            double wdxdy)
+// The cell's terms from its moment sums r = sum f, (jx, jy) = sum f v,
+// E = sum f |v|^2 / 2 (Eq. (10)) and lambda'.
+template <class LV>
+__device__ __forceinline__ AdjCell adj_cell_sums(double r, double jx, double jy, double E, LV&& lv,
+                                                 const Consts& k, double ct, double wdxdy)
 {
-    double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        const double fi = fv(i);
-        r += fi;
-        jx = __builtin_fma(fi, k.vx[i], jx);
-        jy = __builtin_fma(fi, k.vy[i], jy);
-        E = __builtin_fma(fi, k.hv2[i], E);
-    }
     const double ux = jx / r, uy = jy / r;
     const double u2 = ux * ux + uy * uy;
     const double T = E / r - 0.5 * u2;
@@ -521,6 +514,25 @@ __device__ __forceinline__ AdjCell adj_cell(FV&& fv, LV&& lv, const Consts& k, d
     // rest particle: no convection
     c.rest = __builtin_fma(1.0 - ct, l0, c.K0);
     return c;
+}
+
+// The same from f: its sums in the order of k_sums and of the carried-sum
+// step kernels (velocity 0 first), so that sums carried from the forward
+// step give the same terms bit for bit.
+template <class FV, class LV>
+__device__ __forceinline__ AdjCell adj_cell(FV&& fv, LV&& lv, const Consts& k, double ct,
+                                            double wdxdy)
+{
+    double r = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const double fi = fv(i);
+        r += fi;
+        jx = __builtin_fma(fi, k.vx[i], jx);
+        jy = __builtin_fma(fi, k.vy[i], jy);
+        E = __builtin_fma(fi, k.hv2[i], E);
+    }
+    return adj_cell_sums(r, jx, jy, E, lv, k, ct, wdxdy);
 }
 
 // One (tile, group) work item of the reverse step. PS: the K's come from
@@ -591,8 +603,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_
 }
 
 // State pass of the reverse step, one thread per cell: the K's of phase 1
-// (to kst) and the rest particle's adjoint (to plane 0 of lam0).
+// (to kst) and the rest particle's adjoint (to plane 0 of lam0). SUMS: the
+// cell's moment sums come from `sums` ([4][n], as k_sums writes them)
+// instead of from f, which is then not read.
+template <bool SUMS>
 __global__ __launch_bounds__(256) void k_adj_state(const double* __restrict__ f,
+                                                   const double* __restrict__ sums,
                                                    const double* __restrict__ lam1,
                                                    double* __restrict__ lam0,
                                                    double* __restrict__ kst, int64_t n, double ct,
@@ -600,17 +616,21 @@ __global__ __launch_bounds__(256) void k_adj_state(const double* __restrict__ f,
 {
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (c >= n) return;
-    // all 38 values are loaded before any is used, so that their latencies
+    // all values are loaded before any is used, so that their latencies
     // overlap (left to itself the scheduler issues each load just before its
-    // first use and waits for it: 38 round trips in sequence)
-    double fv[NV], lv[NV];
+    // first use and waits for it: one round trip per value in sequence)
+    constexpr int NF = SUMS ? 4 : NV;
+    double fv[NF], lv[NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) fv[i] = f[i * n + c];
+    for (int i = 0; i < NF; ++i) fv[i] = (SUMS ? sums : f)[i * n + c];
 #pragma unroll
     for (int i = 0; i < NV; ++i) lv[i] = lam1[i * n + c];
     __builtin_amdgcn_sched_barrier(0);
-    const AdjCell q = adj_cell([&](int i) { return fv[i]; }, [&](int i) { return lv[i]; }, k, ct,
-                               wdxdy);
+    AdjCell q;
+    if constexpr (SUMS)
+        q = adj_cell_sums(fv[0], fv[1], fv[2], fv[3], [&](int i) { return lv[i]; }, k, ct, wdxdy);
+    else
+        q = adj_cell([&](int i) { return fv[i]; }, [&](int i) { return lv[i]; }, k, ct, wdxdy);
     // the four K's of a cell side by side (32 bytes): the marching kernel
     // takes them with two 16-byte loads
     kst[4 * c] = q.K0;
@@ -1133,9 +1153,10 @@ int adj_variant_desc(int v, int info[4])
     return 0;
 }
 
-hipError_t launch_adjoint(int variant, const double* f, const double* lam1, double* lam0,
-                          double* kst, const Consts& k, int nx, int ny, const int bc[4], double cx,
-                          double cy, double ct, double wdxdy, hipStream_t st)
+hipError_t launch_adjoint(int variant, const double* f, const double* sums, const double* lam1,
+                          double* lam0, double* kst, const Consts& k, int nx, int ny,
+                          const int bc[4], double cx, double cy, double ct, double wdxdy,
+                          hipStream_t st)
 {
     const AdjVariant& V = kAdjVariants[variant];
     AdjArgs a;
@@ -1157,8 +1178,12 @@ hipError_t launch_adjoint(int variant, const double* f, const double* lam1, doub
     a.k = k;
     if (V.PS) {
         const int64_t n = (int64_t)nx * ny;
-        hipLaunchKernelGGL(k_adj_state, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, f,
-                           lam1, lam0, kst, n, ct, wdxdy, k);
+        if (sums)
+            hipLaunchKernelGGL(k_adj_state<true>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                               st, f, sums, lam1, lam0, kst, n, ct, wdxdy, k);
+        else
+            hipLaunchKernelGGL(k_adj_state<false>, dim3((unsigned)((n + 255) / 256)), dim3(256),
+                               0, st, f, sums, lam1, lam0, kst, n, ct, wdxdy, k);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -304,6 +304,53 @@ int lbm_step(lbm_ctx* c, const double* f_in, double* f_out, int32_t nsteps, doub
     return LBM_OK;
 }
 
+int lbm_sums(lbm_ctx* c, const double* f, double* sums, lbm_stream stream)
+{
+    if (!c || !f || !sums) return fail(LBM_EINVAL, "null argument%s%lld");
+    const int64_t n = (int64_t)c->p.nx * c->p.ny;
+    if (overlaps(sums, 4 * n * sizeof(double), f, NV * n * sizeof(double)))
+        return fail(LBM_EINVAL, "sums overlaps f%s%lld");
+    hipError_t e = launch_sums(f, sums, c->k, n, (hipStream_t)stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_sums");
+}
+
+int lbm_step_sums(lbm_ctx* c, const double* f_in, const double* sums_in, double* f_out,
+                  double* sums_out, lbm_stream stream)
+{
+    if (!c || !f_in || !f_out || !sums_out) return fail(LBM_EINVAL, "null argument%s%lld");
+    const int64_t n = (int64_t)c->p.nx * c->p.ny;
+    const size_t fb = NV * n * sizeof(double), sb = 4 * n * sizeof(double);
+    if (overlaps(f_in, fb, f_out, fb) || overlaps(sums_out, sb, f_in, fb) ||
+        overlaps(sums_out, sb, f_out, fb) || (sums_in && (overlaps(sums_in, sb, sums_out, sb) ||
+                                                          overlaps(sums_in, sb, f_out, fb))))
+        return fail(LBM_EINVAL, "an output overlaps an input or another output%s%lld");
+    hipStream_t st = (hipStream_t)stream;
+    const lbm_params& p = c->p;
+    int info[6];
+    step_variant_desc(c->variant, info);
+    const bool carry = p.scheme == LBM_SCHEME_WENO5 && (info[5] == 1 || info[5] == 3);
+    if (!carry) {
+        // the step as lbm_step takes it, then the sums of its result
+        const int rc = lbm_step(c, f_in, f_out, 1, nullptr, stream);
+        if (rc != LBM_OK) return rc;
+        hipError_t e = launch_sums(f_out, sums_out, c->k, n, st);
+        return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_step_sums");
+    }
+    hipError_t e = hipSuccess;
+    if (!sums_in) {
+        e = launch_sums(f_in, c->msum, c->k, n, st);
+        if (e != hipSuccess) return hip_fail(e, "lbm_step_sums");
+        sums_in = c->msum;
+    }
+    if (c->gb[0] || c->gb[1] || c->gb[2] || c->gb[3]) {
+        e = launch_outflow(f_in, p.nx, p.ny, c->gb, c->k, st);
+        if (e != hipSuccess) return hip_fail(e, "lbm_step_sums outflow");
+    }
+    e = launch_step(c->variant, f_in, f_out, c->k, nullptr, p.nx, p.ny, p.bc, p.dt / p.dx,
+                    p.dt / p.dy, p.dt / p.tau, p.ke_axis, c->gb, sums_in, sums_out, st);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_step_sums");
+}
+
 int lbm_moments(lbm_ctx* c, const double* f, double* rho, double* ux, double* uy, double* T,
                 lbm_stream stream)
 {
@@ -405,8 +452,8 @@ int lbmi_default_variant_cells(int64_t cells)
     return 0;
 }
 
-int lbm_adjoint_step(lbm_ctx* c, const double* f_n, const double* lam_np1, double w, double* lam_n,
-                     lbm_stream stream)
+static int adjoint_step(lbm_ctx* c, const double* f_n, const double* sums_n,
+                        const double* lam_np1, double w, double* lam_n, lbm_stream stream)
 {
     if (!c || !f_n || !lam_np1 || !lam_n) return fail(LBM_EINVAL, "null argument%s%lld");
     const lbm_params& p = c->p;
@@ -418,12 +465,27 @@ int lbm_adjoint_step(lbm_ctx* c, const double* f_n, const double* lam_np1, doubl
     if (p.scheme != LBM_SCHEME_WENO5)
         return fail(LBM_EUNSUPPORTED, "the reverse step is the WENO5 scheme's%s%lld");
     const size_t fb = NV * (size_t)p.nx * p.ny * sizeof(double);
-    if (overlaps(lam_n, fb, lam_np1, fb) || overlaps(lam_n, fb, f_n, fb))
+    const size_t sb = 4 * (size_t)p.nx * p.ny * sizeof(double);
+    if (overlaps(lam_n, fb, lam_np1, fb) || overlaps(lam_n, fb, f_n, fb) ||
+        (sums_n && overlaps(lam_n, fb, sums_n, sb)))
         return fail(LBM_EINVAL, "lam_n overlaps an input%s%lld");
-    hipError_t e = launch_adjoint(c->adj_variant, f_n, lam_np1, lam_n, c->msum, c->k, p.nx, p.ny,
-                                  p.bc, p.dt / p.dx, p.dt / p.dy, p.dt / p.tau, w * p.dx * p.dy,
-                                  (hipStream_t)stream);
+    hipError_t e = launch_adjoint(c->adj_variant, f_n, sums_n, lam_np1, lam_n, c->msum, c->k, p.nx,
+                                  p.ny, p.bc, p.dt / p.dx, p.dt / p.dy, p.dt / p.tau,
+                                  w * p.dx * p.dy, (hipStream_t)stream);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_adjoint_step");
+}
+
+int lbm_adjoint_step(lbm_ctx* c, const double* f_n, const double* lam_np1, double w, double* lam_n,
+                     lbm_stream stream)
+{
+    return adjoint_step(c, f_n, nullptr, lam_np1, w, lam_n, stream);
+}
+
+int lbm_adjoint_step_sums(lbm_ctx* c, const double* f_n, const double* sums_n,
+                          const double* lam_np1, double w, double* lam_n, lbm_stream stream)
+{
+    if (!sums_n) return fail(LBM_EINVAL, "null argument%s%lld");
+    return adjoint_step(c, f_n, sums_n, lam_np1, w, lam_n, stream);
 }
 
 int lbm_init_vjp(lbm_ctx* c, const double* rho, const double* ux, const double* uy, const double* T,

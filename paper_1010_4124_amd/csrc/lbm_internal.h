@@ -63,9 +63,12 @@ hipError_t launch_kinetic_part(const double* f, const Consts& k, int64_t n, int 
                                double* part, int* nparts, hipStream_t st);
 int adj_variant_count();
 int adj_variant_desc(int v, int info[4]);
-hipError_t launch_adjoint(int variant, const double* f, const double* lam1, double* lam0,
-                          double* kst, const Consts& k, int nx, int ny, const int bc[4], double cx,
-                          double cy, double ct, double wdxdy, hipStream_t st);
+// sums: NULL, or the moment sums of f ([4][ny][nx], as launch_sums writes
+// them), which the state pass of PS >= 1 variants then reads instead of f
+hipError_t launch_adjoint(int variant, const double* f, const double* sums, const double* lam1,
+                          double* lam0, double* kst, const Consts& k, int nx, int ny,
+                          const int bc[4], double cx, double cy, double ct, double wdxdy,
+                          hipStream_t st);
 hipError_t launch_init_vjp(const double* rho, const double* ux, const double* uy, const double* T,
                            const double* lam, double* grho, double* gux, double* guy, double* gT,
                            const Consts& k, int64_t n, hipStream_t st);

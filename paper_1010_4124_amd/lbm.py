@@ -90,6 +90,8 @@ def lib():
         "lbm_init": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
         "lbm_step": (C.c_int, [_P, _P, _P, _I, _P, _P]),
         "lbm_moments": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+        "lbm_sums": (C.c_int, [_P, _P, _P, _P]),
+        "lbm_step_sums": (C.c_int, [_P, _P, _P, _P, _P, _P]),
         "lbm_kinetic_y": (C.c_int, [_P, _P, _P, _P]),
         "lbm_check_state": (C.c_int, [_P, _P, C.POINTER(C.c_int64), _P]),
         "lbm_kinetic_y_noalloc": (C.c_int, [C.POINTER(LbmParams), _P, _P, _P]),
@@ -98,6 +100,7 @@ def lib():
         "lbm_set_step_variant": (C.c_int, [_P, _I]),
         "lbm_get_step_variant": (C.c_int, [_P, C.POINTER(_I)]),
         "lbm_adjoint_step": (C.c_int, [_P, _P, _P, C.c_double, _P, _P]),
+        "lbm_adjoint_step_sums": (C.c_int, [_P, _P, _P, _P, C.c_double, _P, _P]),
         "lbm_init_vjp": (C.c_int, [_P] + [_P] * 9 + [_P]),
         "lbm_sep_project": (C.c_int, [_P, _P, _P, _I, _P, _P, _P]),
         "lbm_batch_create": (C.c_int, [C.POINTER(LbmParams), _I, C.POINTER(C.c_int64),
@@ -188,6 +191,19 @@ def lbm_step(h, nx, ny, f_in, f_out, nsteps=1, ke_log=None, stream=None):
                           int(nsteps), _ptr(ke_log), _stream(stream)))
 
 
+def lbm_sums(h, nx, ny, f, sums, stream=None):
+    _check(lib().lbm_sums(h, _ptr(f, (NV, ny, nx), "f"), _ptr(sums, (4, ny, nx), "sums"),
+                          _stream(stream)))
+
+
+def lbm_step_sums(h, nx, ny, f_in, sums_in, f_out, sums_out, stream=None):
+    s4 = (4, ny, nx)
+    _check(lib().lbm_step_sums(h, _ptr(f_in, (NV, ny, nx), "f_in"),
+                               None if sums_in is None else _ptr(sums_in, s4, "sums_in"),
+                               _ptr(f_out, (NV, ny, nx), "f_out"), _ptr(sums_out, s4, "sums_out"),
+                               _stream(stream)))
+
+
 def lbm_moments(h, nx, ny, f, rho, ux, uy, T, stream=None):
     s = (ny, nx)
     _check(lib().lbm_moments(h, _ptr(f, (NV, ny, nx), "f"), _ptr(rho, s, "rho"), _ptr(ux, s, "ux"),
@@ -221,6 +237,13 @@ def lbm_adjoint_step(h, nx, ny, f_n, lam_np1, w, lam_n, stream=None):
     s = (NV, ny, nx)
     _check(lib().lbm_adjoint_step(h, _ptr(f_n, s, "f_n"), _ptr(lam_np1, s, "lam_np1"), float(w),
                                   _ptr(lam_n, s, "lam_n"), _stream(stream)))
+
+
+def lbm_adjoint_step_sums(h, nx, ny, f_n, sums_n, lam_np1, w, lam_n, stream=None):
+    s = (NV, ny, nx)
+    _check(lib().lbm_adjoint_step_sums(h, _ptr(f_n, s, "f_n"), _ptr(sums_n, (4, ny, nx), "sums_n"),
+                                       _ptr(lam_np1, s, "lam_np1"), float(w),
+                                       _ptr(lam_n, s, "lam_n"), _stream(stream)))
 
 
 def lbm_init_vjp(h, nx, ny, rho, ux, uy, T, lam0, g_rho, g_ux, g_uy, g_T, stream=None):
@@ -544,6 +567,27 @@ class Context:
         lbm_moments(self.handle, self.nx, self.ny, f, *outs)
         return tuple(outs)
 
+    def empty_sums(self):
+        return torch.empty((4, self.ny, self.nx), dtype=torch.float64, device=self.device)
+
+    def sums(self, f, out=None):
+        """lbm_sums: the moment sums (rho, j_x, j_y, E) of f, [4][ny][nx]."""
+        out = self.empty_sums() if out is None else out
+        lbm_sums(self.handle, self.nx, self.ny, f, out)
+        return out
+
+    def step_sums(self, f, sums=None, out=None, sums_out=None):
+        """lbm_step_sums: one step from f (whose moment sums are `sums`, or
+        None) -> (f_out, the moment sums of f_out)."""
+        out = self.empty_f() if out is None else out
+        sums_out = self.empty_sums() if sums_out is None else sums_out
+        lbm_step_sums(self.handle, self.nx, self.ny, f, sums, out, sums_out)
+        return out, sums_out
+
+    def carries_sums(self):
+        """True when the step variant carries the moment sums (modes 1, 3)."""
+        return lbm_step_variant_info(self.variant)[5] in (1, 3)
+
     def kinetic_y(self, f):
         out = torch.empty(2, dtype=torch.float64, device=self.device)
         lbm_kinetic_y(self.handle, self.nx, self.ny, f, out)
@@ -553,9 +597,14 @@ class Context:
         """lbm_check_state of f: (code, counts)."""
         return lbm_check_state(self.handle, self.nx, self.ny, f, raise_error=raise_error)
 
-    def adjoint_step(self, f_n, lam_np1, w=0.0, out=None):
+    def adjoint_step(self, f_n, lam_np1, w=0.0, out=None, sums=None):
+        """lbm_adjoint_step, or lbm_adjoint_step_sums when the moment sums of
+        f_n are given."""
         out = self.empty_f() if out is None else out
-        lbm_adjoint_step(self.handle, self.nx, self.ny, f_n, lam_np1, w, out)
+        if sums is None:
+            lbm_adjoint_step(self.handle, self.nx, self.ny, f_n, lam_np1, w, out)
+        else:
+            lbm_adjoint_step_sums(self.handle, self.nx, self.ny, f_n, sums, lam_np1, w, out)
         return out
 
     def init_vjp(self, rho, ux, uy, T, lam0):

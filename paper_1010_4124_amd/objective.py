@@ -50,7 +50,8 @@ class Schedule:
         """Live 19-plane states of a gradient: level-1 and level-2
         checkpoints, one piece's states, lambda and its partner; the
         overlapped gradient adds one more piece and one more set of level-2
-        checkpoints."""
+        checkpoints. (With a fast-tile step variant each piece state also
+        keeps its 4 moment-sum planes.)"""
         seq = math.ceil(nsteps / self.K1) + math.ceil(self.K1 / self.K2) + self.K2 + 2
         return seq + (math.ceil(self.K1 / self.K2) + self.K2 if overlap else 0)
 
@@ -120,7 +121,12 @@ class KHIProblem:
     def _recompute(self, ctx, ck, units):
         """States f^s0 .. f^(s1-1) of each unit in turn, recomputed from the
         level-1 checkpoints (and, per level-1 segment, its level-2
-        checkpoints every K2 steps) on ctx."""
+        checkpoints every K2 steps) on ctx, with their moment sums when the
+        step variant is a fast-tile one (mode 3): its single steps then carry
+        the sums from step to step instead of forming them from f each call,
+        and the reverse steps read them instead of f's 19 planes a second
+        time (the sums are lbm_sums's bit for bit, so the gradient is the
+        same either way). Yields (states, sums or None)."""
         K2 = self.schedule.K2
         seg, sub = None, {}
         for c0, c1, s0, s1 in units:
@@ -130,9 +136,17 @@ class KHIProblem:
                     f = ctx.step(f, K2)
                     sub[n] = f
             states = [sub.pop(s0)]
-            for _ in range(s0 + 1, s1):
-                states.append(ctx.step(states[-1], 1))
-            yield states
+            if lbm.lbm_step_variant_info(ctx.variant)[5] == 3:
+                sums = [ctx.sums(states[0])]
+                for _ in range(s0 + 1, s1):
+                    f, m = ctx.step_sums(states[-1], sums[-1])
+                    states.append(f)
+                    sums.append(m)
+            else:
+                sums = None
+                for _ in range(s0 + 1, s1):
+                    states.append(ctx.step(states[-1], 1))
+            yield states, sums
 
     def gradient(self, Dv, Drho, amps, ck=None, scale=1.0, overlap=True):
         """(dJ/dD_v, dJ/dD_rho, dJ/da) by the discrete adjoint.
@@ -154,17 +168,18 @@ class KHIProblem:
         lam_next = ctx.empty_f()
         units = self._units(ck)
 
-        def reverse(unit, states):
+        def reverse(unit, states, sums):
             _, _, s0, s1 = unit
             nonlocal lam, lam_next
             for n in range(s1 - 1, s0 - 1, -1):
-                ctx.adjoint_step(states[n - s0], lam, scale * self.weight(n), out=lam_next)
+                ctx.adjoint_step(states[n - s0], lam, scale * self.weight(n), out=lam_next,
+                                 sums=None if sums is None else sums[n - s0])
                 lam, lam_next = lam_next, lam
 
         if not overlap:
-            for unit, states in zip(units, self._recompute(ctx, ck, units)):
-                reverse(unit, states)
-                del states
+            for unit, (states, sums) in zip(units, self._recompute(ctx, ck, units)):
+                reverse(unit, states, sums)
+                del states, sums
         else:
             main = torch.cuda.current_stream()
             side = torch.cuda.Stream()  # default priority
@@ -186,14 +201,14 @@ class KHIProblem:
 
             ahead = produce()
             for i, unit in enumerate(units):
-                (states, done), ahead = ahead, None
+                ((states, sums), done), ahead = ahead, None
                 if i + 1 < len(units):
                     ahead = produce()  # queued on the side stream before this unit's reverse steps
                 main.wait_event(done)
-                for t in states:
+                for t in states + (sums or []):
                     t.record_stream(main)
-                reverse(unit, states)
-                del states
+                reverse(unit, states, sums)
+                del states, sums
             main.wait_stream(side)
         s = self.fields(Dv, Drho, amps)
         g_rho, g_ux, g_uy, g_T = ctx.init_vjp(*s.fields(), lam)
