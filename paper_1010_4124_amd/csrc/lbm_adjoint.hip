@@ -70,15 +70,24 @@ __device__ __forceinline__ double dweight_c(const Consts& k, int s, double T)
 
 // Reverse mode of one WENO5 face given its shared differences (the same
 // function as weno_face_bar, Eqs. (48)-(55)): g[0..3] are the first
-// differences of the face's five samples, D[0..2] the second differences and
-// E[0..2] = 13/12 D^2 + eps. Returns in Gg[0..3] mu * dh/dg[k] (the centre
-// sample's own term, mu, is added by the caller). Fused multiply-adds
-// throughout and 1/sum(W) from the hardware reciprocal and one Newton step
-// (relative error near 2^-48).
+// differences of the face's five samples, D[0..2] the second differences,
+// CD = 13/12 D and E[0..2] = 13/12 D^2 + eps. Returns in Gg[0..3]
+// mu * dh/dg[k] (the centre sample's own term, mu, is added by the caller).
+//
+// With Q_k = b_k^2 + E (b_k the smoothness indicators' linear parts) and
+// q_k = Q_k^2, the weights d_k / q_k are scaled by 10 q_1 q_2 q_3 into
+// W_1 = q_2 q_3, W_2 = 6 q_1 q_3, W_3 = 3 q_1 q_2, and h = c + sum W_k r_k /
+// sum W_k, r_k the candidate reconstructions less the centre sample c. The
+// factors 6 and 3 are carried by the reconstructions instead (V_2 = q_1 q_3,
+// rho_2 = 6 r_2, ...), and the backward sweep carries a factor 4 (m4 =
+// 4 mu / sum W) that the derivative of q = (b^2 + E)^2 would otherwise
+// multiply in three times; the constants of the last step take it out again.
+// Fused multiply-adds throughout and 1/sum(W) from the hardware reciprocal
+// and one Newton step (relative error near 2^-48).
 __device__ __forceinline__ void weno_face_bar_g(const double (&g)[4], const double (&D)[3],
-                                                const double (&E)[3], double mu, double (&Gg)[4])
+                                                const double (&CD)[3], const double (&E)[3],
+                                                double mu, double (&Gg)[4])
 {
-    constexpr double C13 = 13.0 / 12.0;
     const double b1 = __builtin_fma(0.5, D[0], g[1]);
     const double b2 = 0.5 * (g[1] + g[2]);
     const double b3 = __builtin_fma(0.5, D[2], -g[2]);
@@ -86,39 +95,39 @@ __device__ __forceinline__ void weno_face_bar_g(const double (&g)[4], const doub
     const double Q2 = __builtin_fma(b2, b2, E[1]);
     const double Q3 = __builtin_fma(b3, b3, E[2]);
     const double q1 = Q1 * Q1, q2 = Q2 * Q2, q3 = Q3 * Q3;
-    const double W1 = q2 * q3, W2 = 6.0 * (q1 * q3), W3 = 3.0 * (q1 * q2);
-    const double r1 = __builtin_fma(5.0 / 6.0, g[1], -(1.0 / 3.0) * g[0]);
-    const double r2 = __builtin_fma(1.0 / 6.0, g[1], (1.0 / 3.0) * g[2]);
-    const double r3 = __builtin_fma(2.0 / 3.0, g[2], -(1.0 / 6.0) * g[3]);
-    const double S = W1 + W2 + W3;
+    // W_1, W_2 / 6, W_3 / 3 and r_1, 6 r_2, 3 r_3
+    const double W1 = q2 * q3, V2 = q1 * q3, V3 = q1 * q2;
+    const double p1 = __builtin_fma(5.0 / 6.0, g[1], -(1.0 / 3.0) * g[0]);
+    const double p2 = __builtin_fma(2.0, g[2], g[1]);
+    const double p3 = __builtin_fma(2.0, g[2], -0.5 * g[3]);
+    const double S = __builtin_fma(6.0, V2, __builtin_fma(3.0, V3, W1));
     const double r0 = __builtin_amdgcn_rcp(S);
     const double iden = __builtin_fma(r0, __builtin_fma(-S, r0, 1.0), r0);
-    const double hq = __builtin_fma(W1, r1, __builtin_fma(W2, r2, W3 * r3)) * iden;  // h - c
-    // h = c + (sum W_q r_q) / (sum W_q)
-    const double mi = mu * iden;
-    const double r1b = mi * W1, r2b = mi * W2, r3b = mi * W3;
-    const double W1b = mi * (r1 - hq), W2b6 = 6.0 * (mi * (r2 - hq)),
-                 W3b3 = 3.0 * (mi * (r3 - hq));
-    // W1 = q2 q3, W2 = 6 q1 q3, W3 = 3 q1 q2
-    const double q1b = __builtin_fma(W2b6, q3, W3b3 * q2);
-    const double q2b = __builtin_fma(W1b, q3, W3b3 * q1);
-    const double q3b = __builtin_fma(W1b, q2, W2b6 * q1);
-    // q = Q^2, Q = b^2 + E: dQ = 2 Q dq, db = 2 b dQ, dD (from E) = 2 (13/12) D dQ
-    const double u1 = 4.0 * (Q1 * q1b), u2 = 4.0 * (Q2 * q2b), u3 = 4.0 * (Q3 * q3b);
+    const double hq = __builtin_fma(W1, p1, __builtin_fma(V2, p2, V3 * p3)) * iden;  // h - c
+    const double m4 = 4.0 * (mu * iden);
+    // 4 mu dh/d(p1, p2, p3) and 4 mu dh/d(W1, V2, V3)
+    const double R1 = m4 * W1, R2 = m4 * V2, R3 = m4 * V3;
+    const double A1 = m4 * (p1 - hq), A2 = m4 * __builtin_fma(-6.0, hq, p2),
+                 A3 = m4 * __builtin_fma(-3.0, hq, p3);
+    // u_k = 4 Q_k mu dh/dq_k: mu dh/db_k = b_k u_k, mu dh/dE_k = u_k / 2
+    const double u1 = Q1 * __builtin_fma(A2, q3, A3 * q2);
+    const double u2 = Q2 * __builtin_fma(A1, q3, A3 * q1);
+    const double u3 = Q3 * __builtin_fma(A1, q2, A2 * q1);
     const double b1b = b1 * u1, b2b = b2 * u2, b3b = b3 * u3;
-    // b1 = D0/2 + g1, b2 = (g1 + g2)/2, b3 = D2/2 - g2
-    const double D0b = __builtin_fma(C13 * D[0], u1, 0.5 * b1b);
-    const double D1b = (C13 * D[1]) * u2;
-    const double D2b = __builtin_fma(C13 * D[2], u3, 0.5 * b3b);
-    // r's and b's, then D_k = g_{k+1} - g_k
+    // b1 = D0/2 + g1, b2 = (g1 + g2)/2, b3 = D2/2 - g2; E_k = 13/12 D_k^2 + eps
+    const double D0b = __builtin_fma(CD[0], u1, 0.5 * b1b);
+    const double D1b = CD[1] * u2;
+    const double D2b = __builtin_fma(CD[2], u3, 0.5 * b3b);
+    // p1 = 5/6 g1 - 1/3 g0, p2 = g1 + 2 g2, p3 = 2 g2 - g3 / 2 (R carries 4)
     double g1b = __builtin_fma(0.5, b2b, b1b);
     double g2b = __builtin_fma(0.5, b2b, -b3b);
-    g1b = __builtin_fma(5.0 / 6.0, r1b, __builtin_fma(1.0 / 6.0, r2b, g1b));
-    g2b = __builtin_fma(1.0 / 3.0, r2b, __builtin_fma(2.0 / 3.0, r3b, g2b));
-    Gg[0] = __builtin_fma(-1.0 / 3.0, r1b, -D0b);
+    g1b = __builtin_fma(5.0 / 24.0, R1, __builtin_fma(0.25, R2, g1b));
+    g2b = __builtin_fma(0.5, R2 + R3, g2b);
+    // then D_k = g_{k+1} - g_k
+    Gg[0] = __builtin_fma(-1.0 / 12.0, R1, -D0b);
     Gg[1] = g1b + (D0b - D1b);
     Gg[2] = g2b + (D1b - D2b);
-    Gg[3] = __builtin_fma(-1.0 / 6.0, r3b, D2b);
+    Gg[3] = __builtin_fma(-0.125, R3, D2b);
 }
 
 // Gather of one line strip: fw[0..R+7] are f at strip positions -4..R+3,
@@ -147,7 +156,8 @@ __device__ __forceinline__ void gather_strip(const double (&fw)[R + 8], const do
         // face between strip positions I and I+1: I = t-2 (v >= 0) or R-t (v < 0)
         const double mu = NEG ? cn * (lw[R + 4 - t] - lw[R + 3 - t]) : cn * (lw[t + 2] - lw[t + 1]);
         double Gg[4];
-        weno_face_bar_g(g, D, E, mu, Gg);
+        const double CD[3] = {C13 * D[0], C13 * D[1], C13 * D[2]};
+        weno_face_bar_g(g, D, CD, E, mu, Gg);
         // g_k = P_{t+k+1} - P_{t+k}; the centre sample P_{t+2} adds mu
         Gp[t] -= Gg[0];
         Gp[t + 1] += Gg[0] - Gg[1];
@@ -212,7 +222,8 @@ __device__ __forceinline__ void gather_x_row(const double* s_f, const double* s_
     for (int t = 0; t < R; ++t) {
         const double mu = cnc * (lr[col(t - 1)] - lr[col(t - 2)]);
         double Gg[4];
-        weno_face_bar_g(g, D, E, mu, Gg);
+        const double CD[3] = {C13 * D[0], C13 * D[1], C13 * D[2]};
+        weno_face_bar_g(g, D, CD, E, mu, Gg);
         const double G[5] = {-Gg[0], Gg[0] - Gg[1], (Gg[1] - Gg[2]) + mu, Gg[2] - Gg[3], Gg[3]};
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
@@ -690,10 +701,11 @@ __device__ __forceinline__ void face_g5(double P0, double P1, double P2, double 
     constexpr double C13 = 13.0 / 12.0;
     const double g[4] = {P1 - P0, P2 - P1, P3 - P2, P4 - P3};
     const double D[3] = {g[1] - g[0], g[2] - g[1], g[3] - g[2]};
-    const double E[3] = {__builtin_fma(C13 * D[0], D[0], eps), __builtin_fma(C13 * D[1], D[1], eps),
-                         __builtin_fma(C13 * D[2], D[2], eps)};
+    const double CD[3] = {C13 * D[0], C13 * D[1], C13 * D[2]};
+    const double E[3] = {__builtin_fma(CD[0], D[0], eps), __builtin_fma(CD[1], D[1], eps),
+                         __builtin_fma(CD[2], D[2], eps)};
     double Gg[4];
-    weno_face_bar_g(g, D, E, mu, Gg);
+    weno_face_bar_g(g, D, CD, E, mu, Gg);
     G[0] = -Gg[0];
     G[1] = Gg[0] - Gg[1];
     G[2] = (Gg[1] - Gg[2]) + mu;
@@ -794,11 +806,11 @@ __device__ __forceinline__ void march_velocity(const AdjArgs& a, MarchLds& s, in
     // state at step t: L = lambda' of rows Y0-4+t .. Y0-1+t, Acc[j] = the y
     // sum of row Y0-4+t+j so far (j < 4); g: the first differences of the
     // face's samples v_y f (rows Y0-4+t .. Y0+t) in upwind order, slid from
-    // step to step (the second differences and smoothness terms are formed
-    // from them in each face); Pl: v_y f of row Y0+t; F = f of rows
-    // Y0-4+t .. Y0+t
+    // step to step with the second differences D, 13/12 D and the smoothness
+    // terms E; Pl: v_y f of row Y0+t; F = f of rows Y0-4+t .. Y0+t
     double L[4], Acc[4] = {0.0, 0.0, 0.0, 0.0};
     double Pl = 0.0, g[4] = {0.0, 0.0, 0.0, 0.0}, F[5];
+    double yD[3] = {0.0, 0.0, 0.0}, yC[3] = {0.0, 0.0, 0.0}, yE[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < 4; ++q) L[q] = bload(rl, co, rowt(q));
 #pragma unroll
@@ -810,6 +822,12 @@ __device__ __forceinline__ void march_velocity(const AdjArgs& a, MarchLds& s, in
 #pragma unroll
         for (int q = 0; q < 4; ++q) g[q] = P[q + 1] - P[q];
         Pl = P[NEGY ? 0 : 4];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            yD[q] = g[q + 1] - g[q];
+            yC[q] = C13 * yD[q];
+            yE[q] = __builtin_fma(yC[q], yD[q], eps);
+        }
     }
     // slot k = t mod 2 holds what step t consumes: f of row Y0+1+t,
     // lambda' of row Y0+t and, for the x pass of row Y0-4+t, the edge
@@ -840,12 +858,8 @@ __device__ __forceinline__ void march_velocity(const AdjArgs& a, MarchLds& s, in
             // Y0-4+t.. upwards; v_y < 0: between rows Y0-3+t and Y0-2+t,
             // samples rows Y0+t.. downwards
             const double mu = NEGY ? cy * (L[2] - L[1]) : cy * (L[3] - L[2]);
-            const double D[3] = {g[1] - g[0], g[2] - g[1], g[3] - g[2]};
-            const double E[3] = {__builtin_fma(C13 * D[0], D[0], eps),
-                                 __builtin_fma(C13 * D[1], D[1], eps),
-                                 __builtin_fma(C13 * D[2], D[2], eps)};
             double Gg[4];
-            weno_face_bar_g(g, D, E, mu, Gg);
+            weno_face_bar_g(g, yD, yC, yE, mu, Gg);
             const double G0 = -Gg[0], G1 = Gg[0] - Gg[1], G2 = (Gg[1] - Gg[2]) + mu,
                          G3 = Gg[2] - Gg[3], G4 = Gg[3];
             if constexpr (NEGY) {  // sample q is row Y0+t-q
@@ -898,10 +912,28 @@ __device__ __forceinline__ void march_velocity(const AdjArgs& a, MarchLds& s, in
                 g[2] = g[1];
                 g[1] = g[0];
                 g[0] = Pl - Pn;
+#pragma unroll
+                for (int q = 2; q > 0; --q) {
+                    yD[q] = yD[q - 1];
+                    yC[q] = yC[q - 1];
+                    yE[q] = yE[q - 1];
+                }
+                yD[0] = g[1] - g[0];
+                yC[0] = C13 * yD[0];
+                yE[0] = __builtin_fma(yC[0], yD[0], eps);
             } else {  // the new row is the last sample
 #pragma unroll
                 for (int q = 0; q < 3; ++q) g[q] = g[q + 1];
                 g[3] = Pn - Pl;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    yD[q] = yD[q + 1];
+                    yC[q] = yC[q + 1];
+                    yE[q] = yE[q + 1];
+                }
+                yD[2] = g[3] - g[2];
+                yC[2] = C13 * yD[2];
+                yE[2] = __builtin_fma(yC[2], yD[2], eps);
             }
             Pl = Pn;
         }
