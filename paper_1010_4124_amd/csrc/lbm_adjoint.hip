@@ -1168,7 +1168,8 @@ static const AdjVariant kAdjVariants[] = {
     LBM_ADJ_VARIANT(4, 3, 1, 0) LBM_ADJ_VARIANT(4, 6, 1, 0)
     LBM_ADJ_VARIANT(4, 18, 1, 1) LBM_ADJ_VARIANT(4, 18, 2, 1) LBM_ADJ_VARIANT(2, 18, 2, 1)
     LBM_ADJ_VARIANT(4, 6, 1, 1) LBM_ADJ_VARIANT(4, 3, 1, 1)
-    LBM_ADJ_MARCH(64, 2) LBM_ADJ_MARCH(128, 2) LBM_ADJ_MARCH(256, 2)
+    LBM_ADJ_MARCH(64, 2) LBM_ADJ_MARCH(128, 2) LBM_ADJ_MARCH(256, 2) LBM_ADJ_MARCH(32, 2)
+    LBM_ADJ_MARCH(16, 2)
 };
 #undef LBM_ADJ_VARIANT
 #undef LBM_ADJ_MARCH
