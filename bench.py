@@ -445,8 +445,9 @@ def summarize_adjoint(trace, fetch, write, log_path, commands, sq_dirs=()):
     """Markdown summary of the reverse-step profile: the kernel trace of
     `bench.py --only adjoint` and FETCH_SIZE / WRITE_SIZE passes of
     `bench.py --pmc-run --only adjoint --variant V` (ten 2048^2 reverse
-    steps of variant V: its state pass, band tiles and march or tile kernel),
-    plus any further counter passes of the same command (sq_dirs)."""
+    steps of variant V: its state pass, band tiles and march or tile kernel,
+    then ten given the moment sums of f^n), plus any further counter passes
+    of the same command (sq_dirs)."""
     tab = _capture(trace_table, trace, ["k_adj"])
     ftab = _capture(counter_table, fetch, ["k_adj", "copyBuffer"])
     wtab = _capture(counter_table, write, ["k_adj", "copyBuffer"])
@@ -461,7 +462,14 @@ def summarize_adjoint(trace, fetch, write, log_path, commands, sq_dirs=()):
         w = wr.get((name, grid))
         per.append((name, float(row[4]) * 1024 * sf / n,
                     float(w[4]) * 1024 * sw / n if w else 0.0))
-    rd, wt = sum(p[1] for p in per), sum(p[2] for p in per)
+    # the two forms share the band and march kernels; each has its own state pass
+    st_f, st_s = "lbmd::k_adj_state<false>", "lbmd::k_adj_state<true>"
+    shared = [p for p in per if p[0] not in (st_f, st_s)]
+    forms = []
+    for label, st in (("reverse step", st_f), ("reverse step given the sums", st_s)):
+        pp = shared + [p for p in per if p[0] == st]
+        forms.append((label, sum(p[1] for p in pp), sum(p[2] for p in pp)))
+    (_, rd, wt), (_, rds, wts) = forms
     ev = _bench_line(log_path, "adjoint")
     r2048, r256 = ev["reverse_step_2048"], ev["reverse_step_256"]
     lines = [
@@ -473,14 +481,17 @@ def summarize_adjoint(trace, fetch, write, log_path, commands, sq_dirs=()):
         "chunks of R rows. The bench's tuner picked "
         f"{tuple(r2048['variant'])} at 2048^2 ({r2048['MLUPS']:.0f} MLUPS, "
         f"{1e6 * n / (r2048['MLUPS'] * 1e6):.0f} us per reverse step) and "
-        f"{tuple(r256['variant'])} at 256^2 ({r256['MLUPS']:.0f} MLUPS).",
+        f"{tuple(r256['variant'])} at 256^2 ({r256['MLUPS']:.0f} MLUPS); given the moment sums "
+        f"of f^n, {ev['reverse_step_2048_sums']['MLUPS']:.0f} MLUPS at 2048^2 "
+        f"({1e6 * n / (ev['reverse_step_2048_sums']['MLUPS'] * 1e6):.0f} us).",
         "",
         "## Kernel trace (every variant the tuner tries, both sizes, and the gradients' steps)",
         "",
         "Medians: the traced command also runs the checkpointed gradients, whose reverse steps "
         "overlap the recompute on a second stream.",
         "", tab, "",
-        "## Counter passes, 2048^2, ten reverse steps of the profiled variant",
+        "## Counter passes, 2048^2, ten reverse steps of the profiled variant, then ten given "
+        "the moment sums of f^n",
         "", "FETCH_SIZE (KiB per dispatch):", "", ftab, "",
         "WRITE_SIZE (KiB per dispatch):", "", wtab, "",
         f"Scale factors from the 512 MiB copy in the same runs: FETCH {sf:.4f}, WRITE {sw:.4f}.",
@@ -488,13 +499,16 @@ def summarize_adjoint(trace, fetch, write, log_path, commands, sq_dirs=()):
         "| kernel | read B/cell | written B/cell |",
         "|---|---|---|",
     ] + [f"| `{nm}` | {r:.0f} | {w:.0f} |" for nm, r, w in per] + [
-        f"| reverse step | {rd:.0f} | {wt:.0f} |",
+        f"| {lab} | {r:.0f} | {w:.0f} |" for lab, r, w in forms] + [
         "",
         f"Total {rd + wt:.0f} B per cell against the algorithmic 456 (f^n and lambda^(n+1) read "
         "once, lambda^n written once). The excess is the two-pass structure: the state pass "
         "reads f^n and lambda^(n+1) in full (304 B) and writes the four K's and the rest "
         "plane (40 B); the velocity kernels then read the 18 moving planes of both arrays again "
-        "with their halo rows and strip-edge columns, plus the K's.",
+        "with their halo rows and strip-edge columns, plus the K's. Given the moment sums of "
+        f"f^n, the state pass reads them instead of f^n: {rds + wts:.0f} B per cell in all, against "
+        "the 480 that form must move (the 18 moving planes of f^n, the 4 sums, lambda^(n+1), "
+        "lambda^n).",
     ]
     if sq_dirs:
         lines += ["", "## Further counter passes, 2048^2, the same ten reverse steps", ""]
@@ -610,7 +624,11 @@ def pmc_run(args):
         lam = [torch.randn_like(f0), ctx.empty_f()]
         for q in range(10):
             ctx.adjoint_step(f0, lam[q % 2], 1e-5, out=lam[(q + 1) % 2])
-        del ctx, f0, lam
+        # then ten given the moment sums of f^n (lbm_adjoint_step_sums)
+        sums = ctx.sums(f0)
+        for q in range(10):
+            ctx.adjoint_step(f0, lam[q % 2], 1e-5, out=lam[(q + 1) % 2], sums=sums)
+        del ctx, f0, lam, sums
         torch.cuda.empty_cache()
     else:
         _pmc_main(args, small_setup() if args.only == "forward512" else main_setup())
