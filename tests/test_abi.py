@@ -99,3 +99,13 @@ def test_batch_create_rejects_bad_instances_without_gpu():
     assert create([good, good], [n, 0 + 5]) == lbm.LBM_EINVAL     # overlapping, reversed
     assert create([good, good], [-1, n]) == lbm.LBM_EINVAL        # negative offset
     assert b"overlap" in L.lbm_last_error()
+
+
+def test_sums_entry_points_reject_null_arguments_without_gpu():
+    """lbm_sums, lbm_step_sums and lbm_adjoint_step_sums check their
+    arguments before any device work."""
+    L = lbm.lib()
+    assert L.lbm_sums(None, None, None, None) == lbm.LBM_EINVAL
+    assert L.lbm_step_sums(None, None, None, None, None, None) == lbm.LBM_EINVAL
+    assert L.lbm_adjoint_step_sums(None, None, None, None, 0.0, None, None) == lbm.LBM_EINVAL
+    assert b"null" in L.lbm_last_error()
