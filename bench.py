@@ -476,9 +476,9 @@ def summarize_adjoint(trace, fetch, write, log_path, commands, sq_dirs=()):
         "# Reverse step (discrete adjoint), shear layer at 256^2 and 2048^2: durations and HBM traffic",
         "",
         "Variants (R, G, W, PS): PS = 1 runs lbmd::k_adj_state, then lbmd::k_adjoint<R, G, W, true> "
-        "over 64 x R tiles; PS = 2 runs lbmd::k_adj_state, lbmd::k_adjoint<4, 18, 2, true, true> "
-        "over the tiles next to the walls, and lbmd::k_adj_march<W> over 64-column strips in "
-        "chunks of R rows. The bench's tuner picked "
+        "over 64 x R tiles; PS = 2 runs lbmd::k_adj_state, then lbmd::k_adj_march<W> over "
+        "64-column strips in chunks of R rows, with the tiles next to the walls (the tile "
+        "kernel's code in band mode) in the same launch. The bench's tuner picked "
         f"{tuple(r2048['variant'])} at 2048^2 ({r2048['MLUPS']:.0f} MLUPS, "
         f"{1e6 * n / (r2048['MLUPS'] * 1e6):.0f} us per reverse step) and "
         f"{tuple(r256['variant'])} at 256^2 ({r256['MLUPS']:.0f} MLUPS); given the moment sums "

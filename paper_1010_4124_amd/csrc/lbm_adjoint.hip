@@ -52,6 +52,7 @@ struct AdjArgs {
     double cx, cy, ct, wdxdy;  // w dx dy: weight of the objective term
     FastRect rect;             // marching variants: the marched tiles (64 x 4 units)
     int mh, nstrip, nchunk;    // marching variants: chunk rows, strips, chunks
+    int nband, band_xcd;       // marching variants: band items (all, per XCD)
     Consts k;
 };
 
@@ -549,21 +550,22 @@ __device__ __forceinline__ AdjCell adj_cell(FV&& fv, LV&& lv, const Consts& k, d
 // One (tile, group) work item of the reverse step. PS: the K's come from
 // a.kst (written with the rest plane by k_adj_state). BAND: the tiles are
 // those around a.rect (band_tile), the rest being marched by k_adj_march.
-template <int R, int G, int W, bool PS, bool BAND = false>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_adjoint(AdjArgs a)
-{
-    using SF = StageG<R, FH, AP>;
-    using SL = StageG<R, LH, AP>;
-    __shared__ double s_f[SF::SLOTS];
-    __shared__ double s_l[SL::SLOTS];
-    __shared__ double s_ax[R * AXP];
-    __shared__ double s_xl[R >= 4 ? 256 + 16 * R : 1];  // x faces shared along a row
+template <int R>
+struct TileLds {
+    double f[StageG<R, FH, AP>::SLOTS];
+    double l[StageG<R, LH, AP>::SLOTS];
+    double ax[R * AXP];
+    double xl[R >= 4 ? 256 + 16 * R : 1];  // x faces shared along a row
+};
 
-    const int b = blockIdx.x;
-    const int work = (b & 7) * a.per_xcd + (b >> 3);
-    if (work >= a.nwork) return;
+template <int R, int G, bool PS, bool BAND>
+__device__ __forceinline__ void adjoint_item(const AdjArgs& a, int work, int lane, TileLds<R>& t)
+{
+    double* const s_f = t.f;
+    double* const s_l = t.l;
+    double* const s_ax = t.ax;
+    double* const s_xl = t.xl;
     const int tile = work / G, grp = work - tile * G;
-    const int lane = threadIdx.x;
     const int rm = BAND ? band_tile(tile, a.rect, a.tiles_x, a.tiles_y)
                         : strip_walk(tile, a.tiles_x, a.tiles_y);
     const int ty = rm / a.tiles_x, tx = rm - ty * a.tiles_x;
@@ -611,6 +613,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_
     else
         adj_planes<R, G, true>(a, grp, x0, y0, lane, tf, tl, s_f, s_l, s_ax, s_xl, K0, Kx, Ky,
                                KE);
+}
+
+template <int R, int G, int W, bool PS, bool BAND = false>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_adjoint(AdjArgs a)
+{
+    __shared__ TileLds<R> t;
+    const int b = blockIdx.x;
+    const int work = (b & 7) * a.per_xcd + (b >> 3);
+    if (work >= a.nwork) return;
+    adjoint_item<R, G, PS, BAND>(a, work, threadIdx.x, t);
 }
 
 // State pass of the reverse step, one thread per cell: the K's of phase 1
@@ -1027,12 +1039,25 @@ __device__ __forceinline__ void march_velocity(const AdjArgs& a, MarchLds& s, in
     }
 }
 
+// One launch for the marched region and the band tiles around it: each XCD
+// takes a.per_xcd march items and then a.band_xcd band items (one velocity
+// of a 64 x 4 tile each, k_adjoint's band mode), which fill the tail that
+// the marching waves leave.
 template <int W>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_adj_march(AdjArgs a)
 {
-    __shared__ MarchLds s;
-    const int b = blockIdx.x;
-    const int work = (b & 7) * a.per_xcd + (b >> 3);
+    __shared__ union {
+        MarchLds m;
+        TileLds<4> t;
+    } u;
+    MarchLds& s = u.m;
+    const int b = blockIdx.x, j = b >> 3;
+    if (j >= a.per_xcd) {
+        const int w = (b & 7) * a.band_xcd + (j - a.per_xcd);
+        if (w < a.nband) adjoint_item<4, 18, true, true>(a, w, threadIdx.x, u.t);
+        return;
+    }
+    const int work = (b & 7) * a.per_xcd + j;
     if (work >= a.nwork) return;
     const int reg = work / 18;
     const int i = 1 + (work - reg * 18);
@@ -1231,20 +1256,23 @@ hipError_t launch_adjoint(int variant, const double* f, const double* sums, cons
             a.rect.r0 = a.rect.r1 = a.tiles_y;
         }
         const int nband = band_count(a.rect, a.tiles_x, a.tiles_y);
-        if (nband > 0) {
+        if (a.rect.c1 <= a.rect.c0) {
+            // nothing to march: the band tiles are the whole grid
             a.nwork = nband * 18;
             a.per_xcd = (a.nwork + 7) / 8;
             hipLaunchKernelGGL((k_adjoint<4, 18, 2, true, true>), dim3(8 * a.per_xcd), dim3(64), 0,
                                st, a);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
+            return hipGetLastError();
         }
-        if (a.rect.c1 <= a.rect.c0) return hipSuccess;
         a.mh = V.R;
         a.nstrip = a.rect.c1 - a.rect.c0;
         a.nchunk = ((a.rect.r1 - a.rect.r0) * 4 + V.R - 1) / V.R;
         a.nwork = a.nstrip * a.nchunk * 18;
         a.per_xcd = (a.nwork + 7) / 8;
+        a.nband = nband * 18;
+        a.band_xcd = (a.nband + 7) / 8;
+        hipLaunchKernelGGL(V.kernel, dim3(8 * (a.per_xcd + a.band_xcd)), dim3(64), 0, st, a);
+        return hipGetLastError();
     }
     hipLaunchKernelGGL(V.kernel, dim3(8 * a.per_xcd), dim3(64), 0, st, a);
     return hipGetLastError();
