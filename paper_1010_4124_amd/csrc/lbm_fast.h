@@ -106,13 +106,24 @@ __device__ __forceinline__ void fast_tile_work(const StepGrid& a, const Consts& 
     }
     const double omct = 1.0 - a.ct;
 
-    // rows y0-3 .. y0+R+2 of plane i at the lane's column, and its halo value
-    auto load = [&](int i_in, double(&p)[S::NPRE]) {
+    // the rows of plane i at the lane's column that its faces use, and its
+    // halo value. p[r] is row y0 - 3 + r. The upwind stencils of the R cells
+    // reach rows y0-3 .. y0+R+1 when v_y > 0 and y0-2 .. y0+R+2 when
+    // v_y < 0 (SY, the sign of v_y); with v_y = 0 there are no y faces, and
+    // the x pass reads the R centre rows only
+    auto load = [&](auto sy, int i_in, double(&p)[S::NPRE]) {
+        constexpr int SY = decltype(sy)::value;
+        constexpr int R0 = SY > 0 ? 0 : SY < 0 ? 1 : HALO;
+        constexpr int R1 = SY > 0 ? S::ROWS - 1 : SY < 0 ? S::ROWS : HALO + R;
         const int i = __builtin_amdgcn_readfirstlane(i_in);
         const double* base = a.fin + i * plane + (int64_t)(y0 - HALO) * nx + x0;
 #pragma unroll
-        for (int r = 0; r < S::ROWS; ++r) p[r] = (base + (int64_t)r * nx)[(unsigned)lane];
+        for (int r = R0; r < R1; ++r) p[r] = (base + (int64_t)r * nx)[(unsigned)lane];
         p[S::ROWS] = (a.fin + i * plane + (int64_t)y0 * nx)[(unsigned)hoff];
+    };
+    // the sign of v_y of direction d, as a type
+    auto yrows = [](auto dc) {
+        return std::integral_constant<int, dir_sin_sign(decltype(dc)::value)>{};
     };
 
     // plane of direction d (compile time) in shell s (run time), staged rows
@@ -126,9 +137,9 @@ __device__ __forceinline__ void fast_tile_work(const StepGrid& a, const Consts& 
         const int i = __builtin_amdgcn_readfirstlane(1 + 6 * s + d);
         const double vx = k.vx[i], vy = k.vy[i];
         const double cxv = a.cx * vx, cyv = a.cy * vy;
-        // the staged image for the x pass
+        // the staged image for the x pass (its R centre rows are all it reads)
 #pragma unroll
-        for (int r = 0; r < S::ROWS; ++r) s_pl[r * PITCH + lane + HALO] = p[r];
+        for (int r = HALO; r < HALO + R; ++r) s_pl[r * PITCH + lane + HALO] = p[r];
         s_pl[hslot] = p[S::ROWS];
         // y pass from the registers (y_pass's samples, in the same order)
         double dhy[R], fc[R];
@@ -143,7 +154,10 @@ __device__ __forceinline__ void fast_tile_work(const StepGrid& a, const Consts& 
             for (int j = 0; j < R + 5; ++j) P[j] = SY < 0 ? p[R + 5 - j] : p[j];
             weno_strip<R, (SY < 0)>(P, k.epsy[i], [&](int m, double dd) { dhy[m] = dd; });
         }
-        if constexpr (D == 1) load(next, p);
+        if constexpr (D == 1) {
+            // after the last plane of the last shell there is nothing to load
+            if (d < 5 || next < NV) load(yrows(std::integral_constant<int, (d + 1) % 6>{}), next, p);
+        }
         __syncthreads();
         x_pass<R, NEGX>(s_pl, s_dx, lane, k.epsx[i]);
         __syncthreads();
@@ -175,39 +189,40 @@ __device__ __forceinline__ void fast_tile_work(const StepGrid& a, const Consts& 
     };
 
     // ---- phase 2: the 18 moving velocities, shell by shell
-    auto clamp = [](int j) { return j <= NV - 1 ? j : NV - 1; };  // past the last: re-read it
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    using I4 = std::integral_constant<int, 4>;
+    using I5 = std::integral_constant<int, 5>;
     double pa[S::NPRE], pb[S::NPRE];
-    load(1, pa);
-    if constexpr (D == 2) load(2, pb);
+    load(yrows(I0{}), 1, pa);
+    if constexpr (D == 2) load(yrows(I1{}), 2, pb);
 #pragma unroll 1
     for (int s = 0; s < 3; ++s) {
         const int b1 = 1 + 6 * s;
-        using I0 = std::integral_constant<int, 0>;
-        using I1 = std::integral_constant<int, 1>;
-        using I2 = std::integral_constant<int, 2>;
-        using I3 = std::integral_constant<int, 3>;
-        using I4 = std::integral_constant<int, 4>;
-        using I5 = std::integral_constant<int, 5>;
         if constexpr (D == 1) {
-            do_plane(I0{}, s, pa, clamp(b1 + 1));
-            do_plane(I1{}, s, pa, clamp(b1 + 2));
-            do_plane(I2{}, s, pa, clamp(b1 + 3));
-            do_plane(I3{}, s, pa, clamp(b1 + 4));
-            do_plane(I4{}, s, pa, clamp(b1 + 5));
-            do_plane(I5{}, s, pa, clamp(b1 + 6));
+            do_plane(I0{}, s, pa, b1 + 1);
+            do_plane(I1{}, s, pa, b1 + 2);
+            do_plane(I2{}, s, pa, b1 + 3);
+            do_plane(I3{}, s, pa, b1 + 4);
+            do_plane(I4{}, s, pa, b1 + 5);
+            do_plane(I5{}, s, pa, b1 + 6);
         } else {
             do_plane(I0{}, s, pa, 0);
-            load(clamp(b1 + 2), pa);
+            load(yrows(I2{}), b1 + 2, pa);
             do_plane(I1{}, s, pb, 0);
-            load(clamp(b1 + 3), pb);
+            load(yrows(I3{}), b1 + 3, pb);
             do_plane(I2{}, s, pa, 0);
-            load(clamp(b1 + 4), pa);
+            load(yrows(I4{}), b1 + 4, pa);
             do_plane(I3{}, s, pb, 0);
-            load(clamp(b1 + 5), pb);
+            load(yrows(I5{}), b1 + 5, pb);
             do_plane(I4{}, s, pa, 0);
-            load(clamp(b1 + 6), pa);
+            // the next shell's first two planes (past the last shell: plane
+            // 18 again, unused)
+            load(yrows(I0{}), min(b1 + 6, NV - 1), pa);
             do_plane(I5{}, s, pb, 0);
-            load(clamp(b1 + 7), pb);
+            load(yrows(I1{}), min(b1 + 7, NV - 1), pb);
         }
     }
 
