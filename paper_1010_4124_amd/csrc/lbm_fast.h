@@ -68,16 +68,55 @@ __device__ __forceinline__ void fast_tile_work(const StepGrid& a, const Consts& 
     const int hoff = hr * nx + wrap_once(x0 + hlx, nx);
     const int hslot = hl ? (hr + HALO) * PITCH + hlx + HALO : S::PAD + (lane - 2 * HALO * R);
 
+    // the rows of plane i at the lane's column that its faces use, and its
+    // halo value. p[r] is row y0 - 3 + r. The upwind stencils of the R cells
+    // reach rows y0-3 .. y0+R+1 when v_y > 0 and y0-2 .. y0+R+2 when
+    // v_y < 0 (SY, the sign of v_y); with v_y = 0 there are no y faces, and
+    // the x pass reads the R centre rows only
+    auto load = [&](auto sy, int i_in, double(&p)[S::NPRE]) {
+        constexpr int SY = decltype(sy)::value;
+        constexpr int R0 = SY > 0 ? 0 : SY < 0 ? 1 : HALO;
+        constexpr int R1 = SY > 0 ? S::ROWS - 1 : SY < 0 ? S::ROWS : HALO + R;
+        const int i = __builtin_amdgcn_readfirstlane(i_in);
+        const double* base = a.fin + i * plane + (int64_t)(y0 - HALO) * nx + x0;
+#pragma unroll
+        for (int r = R0; r < R1; ++r) p[r] = (base + (int64_t)r * nx)[(unsigned)lane];
+        p[S::ROWS] = (a.fin + i * plane + (int64_t)y0 * nx)[(unsigned)hoff];
+    };
+    // the sign of v_y of direction d, as a type
+    auto yrows = [](auto dc) {
+        return std::integral_constant<int, dir_sin_sign(decltype(dc)::value)>{};
+    };
+
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    using I4 = std::integral_constant<int, 4>;
+    using I5 = std::integral_constant<int, 5>;
     // ---- phase 1: cell state from the carried sums; rest particle; energy
+    // The carried sums and the rest particle are read by this tile only:
+    // non-temporal loads keep them from displacing halo rows in L2. The
+    // first plane(s) are requested right after them, so that their latency
+    // overlaps phase 1's.
+    double ms[5][R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const int64_t c = (int64_t)(y0 + m) * nx + gx;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ms[q][m] = __builtin_nontemporal_load(&m_in[q * plane + c]);
+        ms[4][m] = __builtin_nontemporal_load(&a.fin[c]);
+    }
+    double pa[S::NPRE], pb[S::NPRE];
+    load(yrows(I0{}), 1, pa);
+    if constexpr (D == 2) load(yrows(I1{}), 2, pb);
+
     double rho[R], Tm[R], uxt[R], uyt[R];  // rho[] holds dt/tau rho
     Sums<R> acc;
     double ke_s = 0.0, ke_m = 0.0;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-        const int64_t c = (int64_t)(y0 + m) * nx + gx;
-        const double r = m_in[c], jx = m_in[plane + c], jy = m_in[2 * plane + c],
-                     E = m_in[3 * plane + c];
-        const double f0 = a.fin[c];
+        const double r = ms[0][m], jx = ms[1][m], jy = ms[2][m], E = ms[3][m], f0 = ms[4][m];
         const CellEq q = cell_eq_from_sums(r, jx, jy, E);
         rho[m] = a.ct * q.rho;
         Tm[m] = q.T;
@@ -105,26 +144,6 @@ __device__ __forceinline__ void fast_tile_work(const StepGrid& a, const Consts& 
         }
     }
     const double omct = 1.0 - a.ct;
-
-    // the rows of plane i at the lane's column that its faces use, and its
-    // halo value. p[r] is row y0 - 3 + r. The upwind stencils of the R cells
-    // reach rows y0-3 .. y0+R+1 when v_y > 0 and y0-2 .. y0+R+2 when
-    // v_y < 0 (SY, the sign of v_y); with v_y = 0 there are no y faces, and
-    // the x pass reads the R centre rows only
-    auto load = [&](auto sy, int i_in, double(&p)[S::NPRE]) {
-        constexpr int SY = decltype(sy)::value;
-        constexpr int R0 = SY > 0 ? 0 : SY < 0 ? 1 : HALO;
-        constexpr int R1 = SY > 0 ? S::ROWS - 1 : SY < 0 ? S::ROWS : HALO + R;
-        const int i = __builtin_amdgcn_readfirstlane(i_in);
-        const double* base = a.fin + i * plane + (int64_t)(y0 - HALO) * nx + x0;
-#pragma unroll
-        for (int r = R0; r < R1; ++r) p[r] = (base + (int64_t)r * nx)[(unsigned)lane];
-        p[S::ROWS] = (a.fin + i * plane + (int64_t)y0 * nx)[(unsigned)hoff];
-    };
-    // the sign of v_y of direction d, as a type
-    auto yrows = [](auto dc) {
-        return std::integral_constant<int, dir_sin_sign(decltype(dc)::value)>{};
-    };
 
     // plane of direction d (compile time) in shell s (run time), staged rows
     // in p; with D = 1, p is refilled with plane `next` once the y pass has
@@ -189,15 +208,6 @@ __device__ __forceinline__ void fast_tile_work(const StepGrid& a, const Consts& 
     };
 
     // ---- phase 2: the 18 moving velocities, shell by shell
-    using I0 = std::integral_constant<int, 0>;
-    using I1 = std::integral_constant<int, 1>;
-    using I2 = std::integral_constant<int, 2>;
-    using I3 = std::integral_constant<int, 3>;
-    using I4 = std::integral_constant<int, 4>;
-    using I5 = std::integral_constant<int, 5>;
-    double pa[S::NPRE], pb[S::NPRE];
-    load(yrows(I0{}), 1, pa);
-    if constexpr (D == 2) load(yrows(I1{}), 2, pb);
 #pragma unroll 1
     for (int s = 0; s < 3; ++s) {
         const int b1 = 1 + 6 * s;
