@@ -112,6 +112,10 @@ __device__ __forceinline__ void fast_tile_work(const StepGrid& a, const Consts& 
     if constexpr (D == 2) load(yrows(I1{}), 2, pb);
 
     double rho[R], Tm[R], uxt[R], uyt[R];  // rho[] holds dt/tau rho
+    // 1 - |u|^2/2T of each cell, and (dt/tau) rho F_k(T) of the shell being
+    // advanced: the same expressions the M = 1 kernel evaluates per plane,
+    // evaluated once per cell and once per cell and shell
+    double t0c[R], Ash[R];
     Sums<R> acc;
     double ke_s = 0.0, ke_m = 0.0;
 #pragma unroll
@@ -122,6 +126,7 @@ __device__ __forceinline__ void fast_tile_work(const StepGrid& a, const Consts& 
         Tm[m] = q.T;
         uxt[m] = q.uxt;
         uyt[m] = q.uyt;
+        t0c[m] = __builtin_fma(-0.5 * q.T, __builtin_fma(q.uxt, q.uxt, q.uyt * q.uyt), 1.0);
         const double un = (a.ke_axis ? jx : jy) / r;
         const double e = 0.5 * r * un * un;
         ke_s += e;
@@ -188,10 +193,7 @@ __device__ __forceinline__ void fast_tile_work(const StepGrid& a, const Consts& 
         for (int m = 0; m < R; ++m) {
             const double dhx = s_dx[m * XPITCH + lane];
             const double eta = __builtin_fma(vx, uxt[m], vy * uyt[m]);
-            const double Am = rho[m] * weight_c(k, s, Tm[m]);
-            const double t0m =
-                __builtin_fma(-0.5 * Tm[m], __builtin_fma(uxt[m], uxt[m], uyt[m] * uyt[m]), 1.0);
-            double fn = __builtin_fma(omct, fc[m], Am * feq_poly(eta, t0m));
+            double fn = __builtin_fma(omct, fc[m], Ash[m] * feq_poly(eta, t0c[m]));
             fn = __builtin_fma(-cxv, dhx, fn);
             fn = __builtin_fma(-cyv, dhy[m], fn);
             acc.r[m] += fn;
@@ -211,6 +213,8 @@ __device__ __forceinline__ void fast_tile_work(const StepGrid& a, const Consts& 
 #pragma unroll 1
     for (int s = 0; s < 3; ++s) {
         const int b1 = 1 + 6 * s;
+#pragma unroll
+        for (int m = 0; m < R; ++m) Ash[m] = rho[m] * weight_c(k, s, Tm[m]);
         if constexpr (D == 1) {
             do_plane(I0{}, s, pa, b1 + 1);
             do_plane(I1{}, s, pa, b1 + 2);
