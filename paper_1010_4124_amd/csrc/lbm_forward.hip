@@ -73,7 +73,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_
         return;
     }
     const int cols = f.c1 - f.c0, rows = f.r1 - f.r0;
-    const int t = strip_walk(work - a.nband, cols, rows);
+    const int t = strip_walk<FAST_STRIP>(work - a.nband, cols, rows);
     const int ty = t / cols, tx = t - ty * cols;
     const int tile = (f.r0 + ty) * a.s.tiles_x + f.c0 + tx;
     // the host's rectangle holds fast tiles only; never stage another here
