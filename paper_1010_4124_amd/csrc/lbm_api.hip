@@ -266,11 +266,9 @@ int lbm_step(lbm_ctx* c, const double* f_in, double* f_out, int32_t nsteps, doub
     step_variant_desc(c->variant, info);
     const int mode = info[5];
     const bool carry = mode == 1 || mode == 3;  // carried moment sums
-    if (carry) {
-        // moment sums of f_in; each step then reads one set and writes the other
-        hipError_t e = launch_sums(f_in, c->msum, c->k, n, st);
-        if (e != hipSuccess) return hip_fail(e, "lbm_step sums");
-    }
+    // carried sums: the first step forms those of f_in (the fast-tile kernel
+    // in its tiles, the others by a sums pass first); each step then reads
+    // one set and writes the other
     for (int s = 0; s < nsteps; ++s) {
         // step s writes f_out when (nsteps - 1 - s) is even, else the scratch
         const double* src = s == 0 ? f_in : (((nsteps - s) % 2 == 0) ? f_out : c->scratch);
@@ -296,7 +294,8 @@ int lbm_step(lbm_ctx* c, const double* f_in, double* f_out, int32_t nsteps, doub
         }
         hipError_t e = launch_step(c->variant, src, dst, c->k,
                                    ke_log && mode != 2 ? ke_row(c, s) : nullptr, p.nx, p.ny, p.bc,
-                                   cx, cy, ct, p.ke_axis, c->gb, m_in, m_out, st);
+                                   cx, cy, ct, p.ke_axis, c->gb, m_in, m_out, st,
+                                   carry && s == 0);
         if (e != hipSuccess) return hip_fail(e, "lbm_step");
         if (ke_log && (e = reduce_ke_rows(c, s, nsteps, nparts, ke_log, st)) != hipSuccess)
             return hip_fail(e, "lbm_step ke");
@@ -337,17 +336,15 @@ int lbm_step_sums(lbm_ctx* c, const double* f_in, const double* sums_in, double*
         return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_step_sums");
     }
     hipError_t e = hipSuccess;
-    if (!sums_in) {
-        e = launch_sums(f_in, c->msum, c->k, n, st);
-        if (e != hipSuccess) return hip_fail(e, "lbm_step_sums");
-        sums_in = c->msum;
-    }
+    // without the sums of f_in the step forms them itself (into c->msum)
+    const bool own = !sums_in;
+    if (own) sums_in = c->msum;
     if (c->gb[0] || c->gb[1] || c->gb[2] || c->gb[3]) {
         e = launch_outflow(f_in, p.nx, p.ny, c->gb, c->k, st);
         if (e != hipSuccess) return hip_fail(e, "lbm_step_sums outflow");
     }
     e = launch_step(c->variant, f_in, f_out, c->k, nullptr, p.nx, p.ny, p.bc, p.dt / p.dx,
-                    p.dt / p.dy, p.dt / p.tau, p.ke_axis, c->gb, sums_in, sums_out, st);
+                    p.dt / p.dy, p.dt / p.tau, p.ke_axis, c->gb, sums_in, sums_out, st, own);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_step_sums");
 }
 

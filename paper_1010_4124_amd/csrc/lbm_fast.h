@@ -43,12 +43,15 @@ struct FastStage {
 
 // Step of fast tile `tile` (row-major index): carried sums in m_in, out,
 // energy partials of the tile into ke_dst (if not null). D planes are in
-// flight ahead of the one being computed (1 or 2).
+// flight ahead of the one being computed (1 or 2). With own_sums the tile
+// forms the moment sums of its cells from f itself (m_in is not read), with
+// the expressions and order of the sums pass (k_sums), so its results are
+// the same bit for bit.
 template <int R, int D, bool NT>
 __device__ __forceinline__ void fast_tile_work(const StepGrid& a, const Consts& k, int tile,
                                                double* ke_dst, double* lds,
                                                const double* __restrict__ m_in,
-                                               double* __restrict__ m_out)
+                                               double* __restrict__ m_out, bool own_sums = false)
 {
     using S = FastStage<R>;
     static_assert(D == 1 || D == 2, "one or two planes in flight");
@@ -100,12 +103,30 @@ __device__ __forceinline__ void fast_tile_work(const StepGrid& a, const Consts& 
     // first plane(s) are requested right after them, so that their latency
     // overlaps phase 1's.
     double ms[5][R];
+    if (own_sums) {
 #pragma unroll
-    for (int m = 0; m < R; ++m) {
-        const int64_t c = (int64_t)(y0 + m) * nx + gx;
+        for (int m = 0; m < R; ++m) ms[0][m] = ms[1][m] = ms[2][m] = ms[3][m] = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) ms[q][m] = __builtin_nontemporal_load(&m_in[q * plane + c]);
-        ms[4][m] = __builtin_nontemporal_load(&a.fin[c]);
+        for (int i = 0; i < NV; ++i) {
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const double fi = a.fin[i * plane + (int64_t)(y0 + m) * nx + gx];
+                if (i == 0) ms[4][m] = fi;
+                ms[0][m] += fi;
+                ms[1][m] = __builtin_fma(fi, k.vx[i], ms[1][m]);
+                ms[2][m] = __builtin_fma(fi, k.vy[i], ms[2][m]);
+                ms[3][m] = __builtin_fma(fi, k.hv2[i], ms[3][m]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int64_t c = (int64_t)(y0 + m) * nx + gx;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                ms[q][m] = __builtin_nontemporal_load(&m_in[q * plane + c]);
+            ms[4][m] = __builtin_nontemporal_load(&a.fin[c]);
+        }
     }
     double pa[S::NPRE], pb[S::NPRE];
     load(yrows(I0{}), 1, pa);

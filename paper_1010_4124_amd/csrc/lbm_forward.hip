@@ -29,6 +29,7 @@ struct StepArgs {
     int nwork, per_xcd;  // work items: tiles (M = 1) or tiles x groups (M = 0, 2)
     int nband;           // M = 3: work items [0, nband) are the tiles around `rect`
     FastRect rect;       // M = 3: the rectangle of fast tiles
+    int own_sums;        // M = 3: fast tiles form the sums of f themselves
     Consts k;
 };
 
@@ -79,7 +80,40 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void k_
     // the host's rectangle holds fast tiles only; never stage another here
     if (!fast_tile(grid_bc(a.s), (f.c0 + tx) * TX, (f.r0 + ty) * R, TX, R, HALO)) return;
     fast_tile_work<R, DEPTH, NT>(a.s, a.k, tile, a.ke_part ? a.ke_part + 2 * tile : nullptr, lds,
-                                 a.m_in, a.m_out);
+                                 a.m_in, a.m_out, a.own_sums != 0);
+}
+
+// Moment sums of the cells of the band tiles around a FastRect (work item w
+// = blockIdx.x, tiles of 64 x R cells), as k_sums forms them: the input sums
+// of a fast-tile step whose fast tiles form their own.
+__global__ __launch_bounds__(64) void k_sums_band(const double* __restrict__ f,
+                                                  double* __restrict__ m, int nx, int ny, int R,
+                                                  FastRect rect, int tiles_x, int tiles_y,
+                                                  Consts k)
+{
+    const int tile = band_tile(blockIdx.x, rect, tiles_x, tiles_y);
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const int x = tx * TX + (int)threadIdx.x;
+    if (x >= nx) return;
+    const int64_t n = (int64_t)nx * ny;
+    for (int r = 0; r < R; ++r) {
+        const int y = ty * R + r;
+        if (y >= ny) break;
+        const int64_t c = (int64_t)y * nx + x;
+        double rho = 0.0, jx = 0.0, jy = 0.0, E = 0.0;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const double fi = f[i * n + c];
+            rho += fi;
+            jx = __builtin_fma(fi, k.vx[i], jx);
+            jy = __builtin_fma(fi, k.vy[i], jy);
+            E = __builtin_fma(fi, k.hv2[i], E);
+        }
+        m[c] = rho;
+        m[n + c] = jx;
+        m[2 * n + c] = jy;
+        m[3 * n + c] = E;
+    }
 }
 
 // State pass of the PH_STATE variants, one thread per cell (state_block).
@@ -349,9 +383,15 @@ int step_ntiles(int variant, int nx, int ny)
 hipError_t launch_step(int variant, const double* fin, double* fout, const Consts& k,
                        double* ke_part, int nx, int ny, const int bc[4], double cx, double cy,
                        double ct, int ke_axis, const double* const gb[4], const double* m_in,
-                       double* m_out, hipStream_t st)
+                       double* m_out, hipStream_t st, bool own_sums)
 {
     const StepVariant& V = kStepVariants[variant];
+    if (own_sums && V.M != PH_FAST) {
+        // only the fast-tile kernel forms sums in its tiles: the sums pass
+        hipError_t e = launch_sums(fin, const_cast<double*>(m_in), k, (int64_t)nx * ny, st);
+        if (e != hipSuccess) return e;
+        own_sums = false;
+    }
     StepArgs a;
     a.s.fin = fin;
     a.s.fout = fout;
@@ -372,6 +412,7 @@ hipError_t launch_step(int variant, const double* fin, double* fout, const Const
     a.tiles_y = (ny + V.R - 1) / V.R;
     a.k = k;
     a.nband = 0;
+    a.own_sums = 0;
     a.rect = FastRect{0, 0, a.tiles_y, a.tiles_y};
     if (V.M == PH_FAST) {
         // the tiles around the rectangle of fast tiles first, then the
@@ -380,6 +421,17 @@ hipError_t launch_step(int variant, const double* fin, double* fout, const Const
         a.nband = band_count(a.rect, a.s.tiles_x, a.tiles_y);
         a.nwork = a.nband + (a.rect.c1 - a.rect.c0) * (a.rect.r1 - a.rect.r0);
         a.per_xcd = (a.nwork + 7) / 8;
+        if (own_sums) {
+            // the band tiles read their sums from m_in: form those first
+            if (a.nband > 0) {
+                hipLaunchKernelGGL(k_sums_band, dim3(a.nband), dim3(64), 0, st, fin,
+                                   const_cast<double*>(m_in), nx, ny, V.R, a.rect, a.s.tiles_x,
+                                   a.tiles_y, k);
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
+            a.own_sums = 1;
+        }
         hipLaunchKernelGGL(V.kernel, dim3(8 * a.per_xcd), dim3(64), 0, st, a);
         return hipGetLastError();
     }

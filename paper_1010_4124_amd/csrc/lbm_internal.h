@@ -39,7 +39,10 @@ int step_ntiles(int variant, int nx, int ny);
 hipError_t launch_step(int variant, const double* fin, double* fout, const Consts& k,
                        double* ke_part, int nx, int ny, const int bc[4], double cx, double cy,
                        double ct, int ke_axis, const double* const gb[4], const double* m_in,
-                       double* m_out, hipStream_t st);
+                       double* m_out, hipStream_t st, bool own_sums = false);
+// own_sums (carried-sum variants): m_in is to receive the moment sums of fin
+// (launch_sums' layout) before the step reads them; the fast-tile kernel
+// forms them in its tiles and writes only those of the band tiles to m_in
 hipError_t launch_step_lo(int scheme, const double* fin, double* fout, const Consts& k,
                           double* ke_part, int* nparts, int nx, int ny, const int bc[4],
                           double cx, double cy, double ct, int ke_axis,
