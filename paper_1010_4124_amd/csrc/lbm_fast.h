@@ -82,9 +82,13 @@ __device__ __forceinline__ void fast_tile_work(const StepGrid& a, const Consts& 
         constexpr int R1 = SY > 0 ? S::ROWS - 1 : SY < 0 ? S::ROWS : HALO + R;
         const int i = __builtin_amdgcn_readfirstlane(i_in);
         const double* base = a.fin + i * plane + (int64_t)(y0 - HALO) * nx + x0;
+        // a raised wave priority while the plane's loads are issued, so that
+        // they are not held back behind the other waves' arithmetic
+        __builtin_amdgcn_s_setprio(1);
+        p[S::ROWS] = (a.fin + i * plane + (int64_t)y0 * nx)[(unsigned)hoff];
 #pragma unroll
         for (int r = R0; r < R1; ++r) p[r] = (base + (int64_t)r * nx)[(unsigned)lane];
-        p[S::ROWS] = (a.fin + i * plane + (int64_t)y0 * nx)[(unsigned)hoff];
+        __builtin_amdgcn_s_setprio(0);
     };
     // the sign of v_y of direction d, as a type
     auto yrows = [](auto dc) {
