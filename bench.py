@@ -244,6 +244,7 @@ def bench_adjoint(args):
         run()
         secs, _ = sync_time(run)
         mlups = n * n * steps / secs / 1e6
+        log(f"adjoint: reverse step {n}^2: {mlups:.0f} MLUPS")
         res[f"reverse_step_{n}"] = {"MLUPS": mlups,
                                     "variant": list(lbm.lbm_adjoint_variant_info(ctx.adj_variant)),
                                     "hbm_frac": mlups * 1e6 * ADJ_BYTES_PER_LUP / 1e9 / HBM_PEAK_GBS}
@@ -273,6 +274,7 @@ def bench_adjoint(args):
     J, ck = prob.run(0.02, 0.02, rng_amps)
     grad_secs, _ = sync_time(lambda: prob.gradient(0.02, 0.02, rng_amps, ck=ck))
     lups = 256 * 256 * args.adj_steps
+    log(f"adjoint: gradient 256^2 done ({grad_secs:.1f} s)")
     res["gradient_256"] = {"steps": args.adj_steps, "checkpoint_every": 200,
                            "forward_MLUPS": lups / fwd_secs / 1e6,
                            "adjoint_MLUPS": lups / grad_secs / 1e6,
@@ -283,10 +285,13 @@ def bench_adjoint(args):
     prob2 = objective.KHIProblem(2048, 2048, nsteps=n2, window=(n2 // 2, n2),
                                  schedule=objective.Schedule.sqrt(n2))
     tune_problem(prob2)
+    log(f"adjoint: 2048^2, {n2} steps, schedule {prob2.schedule.K1} x {prob2.schedule.K2}: tuned")
     amps2 = inputs.mode_amplitudes(2048, seed=7)
     fsecs, _ = sync_time(lambda: prob2.run(0.01, 0.04, amps2, keep_checkpoints=False))
+    log(f"adjoint: 2048^2 forward run {fsecs:.1f} s")
     torch.cuda.reset_peak_memory_stats()
     J2, ck2 = prob2.run(0.01, 0.04, amps2)
+    log("adjoint: 2048^2 forward run with checkpoints done")
     grad2 = []
     gsecs, _ = sync_time(lambda: grad2.append(prob2.gradient(0.01, 0.04, amps2, ck=ck2)))
     gDv2, gDrho2, ga2 = grad2[0]
@@ -488,7 +493,8 @@ def summarize_adjoint(trace, fetch, write, log_path, commands, sq_dirs=()):
         "## Kernel trace (every variant the tuner tries, both sizes, and the gradients' steps)",
         "",
         "Medians: the traced command also runs the checkpointed gradients, whose reverse steps "
-        "overlap the recompute on a second stream.",
+        "overlap the recompute on a second stream on the 256^2 grid (not at 2048^2, which the "
+        "GPU's share of either fills alone).",
         "", tab, "",
         "## Counter passes, 2048^2, ten reverse steps of the profiled variant, then ten given "
         "the moment sums of f^n",

@@ -148,14 +148,24 @@ class KHIProblem:
                     states.append(ctx.step(states[-1], 1))
             yield states, sums
 
-    def gradient(self, Dv, Drho, amps, ck=None, scale=1.0, overlap=True):
+    # grids from this many cells on fill the GPU alone: no overlapped recompute
+    OVERLAP_MAX_CELLS = 1 << 20
+
+    def gradient(self, Dv, Drho, amps, ck=None, scale=1.0, overlap=None):
         """(dJ/dD_v, dJ/dD_rho, dJ/da) by the discrete adjoint.
 
         overlap: recompute the next unit's states on a second context and
         stream while the current unit's reverse steps run (the two are
         independent), so that grids too small to fill the GPU alone share it;
         at most one more unit's states and one more segment's level-2
-        checkpoints are alive. The result is the same bit for bit."""
+        checkpoints are alive. The result is the same bit for bit. None (the
+        default): overlap below OVERLAP_MAX_CELLS cells only. On larger grids
+        the overlap gains little, and the states it frees on one stream after
+        use on the other are not reused by torch's caching allocator soon
+        enough: at 2048^2 x 4000 steps it reserved 250 GB for 45 GB in use,
+        and a 40000-step gradient ran out of room and slowed down."""
+        if overlap is None:
+            overlap = self.nx * self.ny < self.OVERLAP_MAX_CELLS
         if ck is None:
             _, ck = self.run(Dv, Drho, amps)
         ctx = self.ctx
