@@ -302,7 +302,10 @@ def bench_adjoint(args):
                             "finite": bool(np.isfinite([J2, gDv2, gDrho2]).all()
                                            and np.isfinite(ga2).all()),
                             "J": J2, "dJ_dDv": gDv2, "dJ_dDrho": gDrho2,
-                            "variants": _variants(prob2.ctx)}
+                            "variants": _variants(prob2.ctx),
+                            "note": ("configuration 5 at full length" if n2 >= 40000 else
+                                     f"a {n2}-step sample of configuration 5 (40000 steps: "
+                                     "--only adjoint --adj-large-steps 40000)")}
     log(f"adjoint: {res}")
     del prob, prob2, ck, ck2
     torch.cuda.empty_cache()
