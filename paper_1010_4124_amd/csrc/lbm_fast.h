@@ -176,8 +176,8 @@ __device__ __forceinline__ void fast_tile_work(const StepGrid& a, const Consts& 
     const double omct = 1.0 - a.ct;
 
     // plane of direction d (compile time) in shell s (run time), staged rows
-    // in p; with D = 1, p is refilled with plane `next` once the y pass has
-    // consumed it
+    // in p; with D = 1, p is refilled with plane `next` once its rows are
+    // staged and copied for the y pass
     auto do_plane = [&](auto dc, int s, double(&p)[S::NPRE], int next) {
         constexpr int d = decltype(dc)::value;
         constexpr bool NEGX = dir_cos(d) < 0.0;
@@ -197,16 +197,19 @@ __device__ __forceinline__ void fast_tile_work(const StepGrid& a, const Consts& 
             fc[m] = p[m + HALO];
             dhy[m] = 0.0;
         }
+        // the y pass works on a copy of the rows, so that the next plane's
+        // loads (D = 1) are issued into p before it rather than after it
+        double P[SY != 0 ? R + 5 : 1];
         if constexpr (SY != 0) {
-            double P[R + 5];
 #pragma unroll
             for (int j = 0; j < R + 5; ++j) P[j] = SY < 0 ? p[R + 5 - j] : p[j];
-            weno_strip<R, (SY < 0)>(P, k.epsy[i], [&](int m, double dd) { dhy[m] = dd; });
         }
         if constexpr (D == 1) {
             // after the last plane of the last shell there is nothing to load
             if (d < 5 || next < NV) load(yrows(std::integral_constant<int, (d + 1) % 6>{}), next, p);
         }
+        if constexpr (SY != 0)
+            weno_strip<R, (SY < 0)>(P, k.epsy[i], [&](int m, double dd) { dhy[m] = dd; });
         __syncthreads();
         x_pass<R, NEGX>(s_pl, s_dx, lane, k.epsx[i]);
         __syncthreads();
