@@ -255,8 +255,12 @@ int lbm_sep_project(lbm_ctx* ctx, const double* g, const double* A, int32_t M, c
  *      workgroup;
  *   2  a state pass per step forms the cell state (dt/tau rho, T, u/T, v/T),
  *      updates the rest particle and the energy partials; every (tile, group)
- *      workgroup then reads the state.
- * The context holds two [4][ny][nx] buffers for modes 1 and 2. Every variant
+ *      workgroup then reads the state;
+ *   3  as 1 (G = 1), with the tiles whose stencils need no boundary rule
+ *      advanced by a fast-tile body that takes all 18 velocities in one
+ *      wavefront; a call's first step forms the sums of f_in in those tiles
+ *      (in lbm_sums's order) and, for the tiles around them, in a small pass.
+ * The context holds two [4][ny][nx] buffers for modes 1, 2 and 3. Every variant
  * evaluates the same formulas; results agree to rounding (the WENO face
  * arithmetic is grouped per strip of R cells and the moment sums per wave),
  * and a given variant is deterministic. lbm_set_step_variant selects the
