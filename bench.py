@@ -496,8 +496,8 @@ def summarize_adjoint(trace, fetch, write, log_path, commands, sq_dirs=()):
         "## Kernel trace (every variant the tuner tries, both sizes, and the gradients' steps)",
         "",
         "Medians: the traced command also runs the checkpointed gradients, whose reverse steps "
-        "overlap the recompute on a second stream on the 256^2 grid (not at 2048^2, which the "
-        "GPU's share of either fills alone).",
+        "overlap the recompute on a second stream on the 256^2 grid (not at 2048^2, a grid that "
+        "fills the GPU by itself).",
         "", tab, "",
         "## Counter passes, 2048^2, ten reverse steps of the profiled variant, then ten given "
         "the moment sums of f^n",
